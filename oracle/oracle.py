@@ -1,0 +1,177 @@
+"""ctypes wrapper around the FP64 CPU oracle (``gini_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the package smoke check and the
+benchmark's CPU-baseline leg are the only callers.  The product path never
+imports this module, and this module imports nothing from the product.
+
+``build()`` compiles ``gini_oracle.c`` with plain ``gcc -O2`` (no fast-math,
+no FMA contraction, single thread) into ``liboracle.so`` next to it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "gini_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+EXACT = 0
+MATCH32 = 1
+LATENT_GINI = 0
+LATENT_EUCLID = 1
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle shared library (always, when ``force``)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+               "-o", tmp, SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build(force=True)
+        L = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        i32 = ctypes.c_int
+        f64 = ctypes.c_double
+        L.orc_rank2_count.argtypes = [P, i32, P]
+        L.orc_rank2_sort.argtypes = [P, i32, P]
+        L.orc_rank2.argtypes = [P, i32, P]
+        L.orc_rank2_rows.argtypes = [P, i64, i32, i64, P, i64]
+        L.orc_gini_dist.argtypes = [P, i32, f64]
+        L.orc_gini_dist.restype = f64
+        L.orc_gini_dist_grad.argtypes = [P, i32, f64, P]
+        L.orc_gini_dist_grad.restype = f64
+        L.orc_gini_asym.argtypes = [P, i32, f64]
+        L.orc_gini_asym.restype = f64
+        L.orc_dissim.argtypes = [P, i64, i32, i64, i32, P, i32, P, i64, i64]
+        L.orc_dissim_pairs.argtypes = [P, i32, i64, i32, P, P, i64, P, i32, P]
+        L.orc_stress.argtypes = [P, i64, i64, P, i32, i64, f64, i32, i32, P, i64]
+        L.orc_stress.restype = f64
+        L.orc_grad_rows.argtypes = [P, i64, P, i64, i64, P, i32, i64, f64, i32, i32, P, i64]
+        L.orc_grad_rows.restype = f64
+        L.orc_step_size.argtypes = [i64, i32, f64, i32]
+        L.orc_step_size.restype = f64
+        L.orc_solve.argtypes = [P, i64, i64, P, i32, i64, f64, i32, i32, i32, f64, P]
+        _lib = L
+    return _lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def rank2(v, method: str = "auto") -> np.ndarray:
+    """Doubled midranks t = 2R of one vector."""
+    v = _f64(v).reshape(-1)
+    t = np.empty(v.shape[0], dtype=np.int32)
+    fn = {"auto": lib().orc_rank2, "count": lib().orc_rank2_count, "sort": lib().orc_rank2_sort}[method]
+    fn(_ptr(v), int(v.shape[0]), _ptr(t))
+    return t
+
+
+def rank2_rows(V) -> np.ndarray:
+    """Doubled midranks of every row of a 2-D array."""
+    V = _f64(V)
+    rows, d = V.shape
+    t = np.empty((rows, d), dtype=np.int32)
+    lib().orc_rank2_rows(_ptr(V), rows, d, d, _ptr(t), d)
+    return t
+
+
+def gini_dist(z, nu: float) -> float:
+    z = _f64(z).reshape(-1)
+    return float(lib().orc_gini_dist(_ptr(z), int(z.shape[0]), float(nu)))
+
+
+def gini_dist_grad(z, nu: float):
+    z = _f64(z).reshape(-1)
+    g = np.empty_like(z)
+    v = lib().orc_gini_dist_grad(_ptr(z), int(z.shape[0]), float(nu), _ptr(g))
+    return float(v), g
+
+
+def gini_asym(z, nu: float) -> float:
+    z = _f64(z).reshape(-1)
+    return float(lib().orc_gini_asym(_ptr(z), int(z.shape[0]), float(nu)))
+
+
+def dissim(X, nus, mode: int = MATCH32) -> np.ndarray:
+    """Full symmetric dissimilarity matrices, shape (len(nus), n, n)."""
+    X = _f64(X)
+    n, m = X.shape
+    nus_a = _f64(list(nus))
+    out = np.empty((len(nus_a), n, n), dtype=np.float64)
+    lib().orc_dissim(_ptr(X), n, m, m, mode, _ptr(nus_a), len(nus_a), _ptr(out), n, n * n)
+    return out
+
+
+def dissim_pairs(X, pi, pj, nus, mode: int = MATCH32) -> np.ndarray:
+    """Distances for explicit pairs, shape (npairs, len(nus))."""
+    X = _f64(X)
+    n, m = X.shape
+    pi = np.ascontiguousarray(pi, dtype=np.int64)
+    pj = np.ascontiguousarray(pj, dtype=np.int64)
+    nus_a = _f64(list(nus))
+    out = np.empty((pi.shape[0], len(nus_a)), dtype=np.float64)
+    lib().orc_dissim_pairs(_ptr(X), m, m, mode, _ptr(pi), _ptr(pj), pi.shape[0], _ptr(nus_a),
+                           len(nus_a), _ptr(out))
+    return out
+
+
+def stress(Delta, Z, nu: float, latent: int = LATENT_GINI, mode: int = MATCH32, grad: bool = True):
+    """(sigma, G) with sigma = sum_{i<j} (delta_ij - Delta_ij)^2 and G its gradient."""
+    D = _f64(Delta)
+    Z = _f64(Z)
+    n, p = Z.shape
+    G = np.empty((n, p), dtype=np.float64) if grad else None
+    s = lib().orc_stress(_ptr(D), n, D.shape[1], _ptr(Z), p, p, float(nu), latent, mode,
+                         _ptr(G) if grad else None, p)
+    return float(s), G
+
+
+def grad_rows(Drows, rows, Z, nu: float, latent: int = LATENT_GINI, mode: int = MATCH32):
+    """Gradient rows G[rows] from the corresponding rows of Delta; also returns
+    the partial sum over the selected rows of sum_{j>i} r_ij^2."""
+    D = _f64(Drows)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    Z = _f64(Z)
+    n, p = Z.shape
+    G = np.empty((rows.shape[0], p), dtype=np.float64)
+    part = lib().orc_grad_rows(_ptr(D), D.shape[1], _ptr(rows), rows.shape[0], n, _ptr(Z), p, p,
+                               float(nu), latent, mode, _ptr(G), p)
+    return G, float(part)
+
+
+def step_size(n: int, p: int, nu: float, latent: int = LATENT_GINI) -> float:
+    return float(lib().orc_step_size(n, p, float(nu), latent))
+
+
+def solve(Delta, Z0, nu: float, iters: int, latent: int = LATENT_GINI, mode: int = MATCH32,
+          eta: float = 0.0):
+    """Fixed-step gradient descent; returns (Z_T, sigma history)."""
+    D = _f64(Delta)
+    Z = _f64(Z0).copy()
+    n, p = Z.shape
+    hist = np.empty(iters, dtype=np.float64)
+    lib().orc_solve(_ptr(D), n, D.shape[1], _ptr(Z), p, p, float(nu), latent, mode, iters,
+                    float(eta), _ptr(hist))
+    return Z, hist

@@ -1,0 +1,328 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these tests retypes the oracle's own formula: each checks it against a
+printed value, a rank-free identity, a library routine, a closed form, a
+property the paper proves, or brute force.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy.spatial.distance import pdist, squareform
+from scipy.stats import rankdata
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+NUS = [1.1, 1.5, 2.0, 3.0, 3.7, 5.0]
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+# ------------------------------------------------------------------ ranks
+def test_rank_worked_example(orc):
+    g = _gold("worked_example.json")
+    z = np.array(g["u"]) - np.array(g["v"])
+    assert list(orc.rank2(z)) == [2 * r for r in g["ranks_of_u_minus_v"]]
+
+
+def test_rank_zero_vector_is_midpoint(orc):
+    g = _gold("rank_zero_vector.json")
+    for d in g["dims"]:
+        t = orc.rank2(np.zeros(d))
+        assert np.all(t == d + 1)            # t = 2R = d+1
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 5, 16, 63, 64, 65, 200, 784])
+def test_rank_matches_scipy_average(orc, d):
+    g = np.random.Generator(np.random.PCG64(11 + d))
+    for levels in (None, 2, 6):
+        v = g.standard_normal(d) if levels is None else g.integers(-levels, levels + 1, d).astype(float)
+        ref = (2 * rankdata(v, method="average")).astype(np.int64)
+        assert np.array_equal(orc.rank2(v, "sort"), ref)
+        if d <= 300:
+            assert np.array_equal(orc.rank2(v, "count"), ref)
+        assert np.array_equal(orc.rank2(v), ref)
+
+
+@pytest.mark.parametrize("d", [1, 2, 7, 64, 100])
+def test_rank_invariants(orc, d):
+    g = np.random.Generator(np.random.PCG64(5 * d))
+    v = g.integers(-3, 4, d).astype(float)
+    t = orc.rank2(v).astype(np.int64)
+    assert t.sum() == d * (d + 1)                              # sum of ranks
+    assert np.array_equal(orc.rank2(-v), 2 * d + 2 - t)         # R(-x) = d+1-R(x)
+    assert np.all(orc.rank2(np.full(d, 3.25)) == d + 1)         # all tied
+
+
+def test_rank_signed_zero_ties(orc):
+    t = orc.rank2(np.array([0.0, -0.0, 1.0, -1.0]))
+    assert list(t) == [5, 5, 8, 2]          # -1 < (0 == -0) < 1
+
+
+# ------------------------------------------------------- the distance
+def test_worked_example_distance(orc):
+    g = _gold("worked_example.json")
+    u, v = np.array(g["u"]), np.array(g["v"])
+    assert orc.gini_dist(u - v, g["nu"]) == g["D_G"]
+    assert orc.gini_dist(v - u, g["nu"]) == g["D_G"]
+    assert orc.gini_asym(u - v, g["nu"]) == g["D_G"]
+
+
+@pytest.mark.parametrize("d", [2, 3, 10, 64, 97])
+def test_nu2_is_half_gini_mean_difference(orc, d):
+    """At nu=2 the distance is (1/2) sum_{a<b} |z_a - z_b|: rank-free, tie-free or not."""
+    g = np.random.Generator(np.random.PCG64(100 + d))
+    for levels in (None, 3):
+        z = g.standard_normal(d) if levels is None else g.integers(-levels, levels + 1, d).astype(float)
+        gmd = 0.5 * sum(abs(z[a] - z[b]) for a in range(d) for b in range(a + 1, d))
+        assert orc.gini_dist(z, 2.0) == pytest.approx(gmd, rel=1e-12, abs=1e-12)
+
+
+@pytest.mark.parametrize("d", [2, 5, 33])
+def test_nu2_is_definition2_with_library_midranks(orc, d):
+    g = np.random.Generator(np.random.PCG64(7 + d))
+    z = g.integers(-2, 3, d).astype(float)
+    dg = float(np.sum(z * (rankdata(z, method="average") - (d + 1) / 2.0)))
+    assert orc.gini_dist(z, 2.0) == pytest.approx(dg, rel=1e-12, abs=1e-12)
+    assert orc.gini_asym(z, 2.0) == pytest.approx(dg, rel=1e-12, abs=1e-12)
+
+
+@pytest.mark.parametrize("nu", NUS)
+def test_closed_form_d2(orc, nu):
+    g = np.random.Generator(np.random.PCG64(3))
+    for _ in range(20):
+        z = g.standard_normal(2)
+        assert orc.gini_dist(z, nu) == pytest.approx(2.0 ** (1 - nu) * abs(z[0] - z[1]), rel=1e-12)
+    assert orc.gini_dist([1.5, 1.5], nu) == 0.0
+
+
+@pytest.mark.parametrize("nu", NUS)
+def test_closed_form_d3(orc, nu):
+    g = np.random.Generator(np.random.PCG64(4))
+    for _ in range(20):
+        z = g.standard_normal(3)
+        ref = 1.5 * (2.0 / 3.0) ** (nu - 1) * (z.max() - z.min())
+        assert orc.gini_dist(z, nu) == pytest.approx(ref, rel=1e-12)
+    # a tie at the bottom: two coordinates share doubled rank 3, the third has 6
+    z = np.array([-5.0, -5.0, -4.0])
+    w3 = (1 / 6) ** (nu - 1) - (1 / 2) ** (nu - 1)
+    w6 = (2 / 3) ** (nu - 1)
+    ref = 1.5 * (2 * w3 * -5.0 + w6 * -4.0)
+    assert orc.gini_dist(z, nu) == pytest.approx(ref, rel=1e-12, abs=1e-12)
+
+
+def test_ties_can_break_nonnegativity_off_nu2(orc):
+    assert orc.gini_dist([-5.0, -5.0, -4.0], 1.5) < 0.0
+    assert orc.gini_dist([-5.0, -5.0, -4.0], 2.0) >= 0.0
+
+
+@pytest.mark.parametrize("nu", NUS)
+def test_d1_is_zero(orc, nu):
+    assert orc.gini_dist([3.0], nu) == 0.0
+
+
+@pytest.mark.parametrize("nu", NUS)
+def test_pseudometric_properties(orc, nu):
+    """Proposition 2 / 3: null, egalitarian, symmetry, homogeneity, triangle and
+    non-negativity (tie-free data for nu != 2)."""
+    g = np.random.Generator(np.random.PCG64(int(nu * 10)))
+    d = 9
+    assert orc.gini_dist(np.zeros(d), nu) == 0.0
+    assert orc.gini_dist(np.full(d, -2.5), nu) == 0.0
+    for _ in range(40):
+        x, y, w = g.standard_normal((3, d))
+        dxy = orc.gini_dist(x - y, nu)
+        assert dxy == orc.gini_dist(y - x, nu)
+        assert dxy >= 0.0
+        lam = g.uniform(-3, 3)
+        assert orc.gini_dist(lam * (x - y), nu) == pytest.approx(abs(lam) * dxy, rel=1e-12, abs=1e-14)
+        assert dxy <= orc.gini_dist(x - w, nu) + orc.gini_dist(w - y, nu) + 1e-12
+
+
+def test_pseudometric_with_ties_at_nu2(orc):
+    g = np.random.Generator(np.random.PCG64(77))
+    for _ in range(40):
+        x, y, w = g.integers(-2, 3, (3, 8)).astype(float)
+        dxy = orc.gini_dist(x - y, 2.0)
+        assert dxy >= 0.0
+        assert dxy <= orc.gini_dist(x - w, 2.0) + orc.gini_dist(w - y, 2.0) + 1e-12
+
+
+@pytest.mark.parametrize("nu", [1.5, 2.0, 3.7])
+def test_support_function_inequality(orc, nu):
+    """With ranks frozen the distance is linear; over tie-free points it is the
+    maximum of these linear pieces (the rearrangement argument of the proofs),
+    so delta(z) >= a(z') . z for every z'."""
+    g = np.random.Generator(np.random.PCG64(9))
+    for _ in range(30):
+        z, z2 = g.standard_normal((2, 6))
+        dz = orc.gini_dist(z, nu)
+        _, a2 = orc.gini_dist_grad(z2, nu)
+        assert dz >= float(a2 @ z) - 1e-12
+        # brute force over every ordering of the weights of z2
+        best = max(float(np.dot(z, a2[list(perm)])) for perm in itertools.permutations(range(6)))
+        assert dz == pytest.approx(best, rel=1e-12)
+
+
+@pytest.mark.parametrize("nu", [1.3, 2.0, 4.2])
+def test_distance_gradient_finite_difference(orc, nu):
+    g = np.random.Generator(np.random.PCG64(21))
+    for d in (2, 3, 7):
+        z = g.standard_normal(d)
+        _, a = orc.gini_dist_grad(z, nu)
+        h = 1e-7
+        for c in range(d):
+            e = np.zeros(d)
+            e[c] = h
+            fd = (orc.gini_dist(z + e, nu) - orc.gini_dist(z - e, nu)) / (2 * h)
+            assert fd == pytest.approx(a[c], rel=1e-6, abs=1e-8)
+
+
+def test_match32_decides_on_float_bits(orc):
+    X = np.array([[1.0 + 2.0 ** -30, 0.0], [1.0, 0.0]])
+    D32 = orc.dissim(X, [3.0], orc.MATCH32)
+    D64 = orc.dissim(X, [3.0], orc.EXACT)
+    assert D32[0, 0, 1] == 0.0                      # the difference rounds to 0 in FP32
+    assert D64[0, 0, 1] > 0.0
+
+
+def test_dissim_matrix_structure(orc):
+    g = np.random.Generator(np.random.PCG64(31))
+    X = g.standard_normal((13, 6))
+    D = orc.dissim(X, [1.5, 2.0], orc.EXACT)
+    for k, nu in enumerate([1.5, 2.0]):
+        assert np.array_equal(D[k], D[k].T)
+        assert np.all(np.diag(D[k]) == 0.0)
+        i, j = np.triu_indices(13, 1)
+        P = orc.dissim_pairs(X, i, j, [nu], orc.EXACT)[:, 0]
+        assert np.array_equal(P, D[k][i, j])
+        assert D[k][0, 5] == orc.gini_dist(X[0] - X[5], nu)
+
+
+# ---------------------------------------------------------- the stress
+def _problem(seed, n, m, p):
+    g = np.random.Generator(np.random.PCG64(seed))
+    X = g.standard_normal((n, m))
+    Z = 0.5 * g.standard_normal((n, p))
+    return X, Z
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_euclid_stress_matches_pdist(orc, p):
+    X, Z = _problem(1, 25, 5, p)
+    D = orc.dissim(X, [2.0], orc.EXACT)[0]
+    s, _ = orc.stress(D, Z, 2.0, orc.LATENT_EUCLID, orc.EXACT)
+    ref = float(np.sum((pdist(Z) - squareform(D, checks=False)) ** 2))
+    assert s == pytest.approx(ref, rel=1e-12)
+
+
+@pytest.mark.parametrize("nu", [1.5, 2.0, 3.0])
+def test_gini_p2_stress_closed_form(orc, nu):
+    X, Z = _problem(2, 30, 4, 2)
+    D = orc.dissim(X, [nu], orc.EXACT)[0]
+    s, _ = orc.stress(D, Z, nu, orc.LATENT_GINI, orc.EXACT)
+    u = Z[:, None, :] - Z[None, :, :]
+    delta = 2.0 ** (1 - nu) * np.abs(u[..., 0] - u[..., 1])
+    i, j = np.triu_indices(30, 1)
+    ref = float(np.sum((delta[i, j] - D[i, j]) ** 2))
+    assert s == pytest.approx(ref, rel=1e-12)
+
+
+@pytest.mark.parametrize("latent,p,nu", [(0, 2, 2.0), (0, 3, 1.5), (0, 3, 3.7), (1, 2, 2.0), (1, 3, 3.0)])
+def test_stress_gradient_finite_difference(orc, latent, p, nu):
+    X, Z = _problem(3 + p, 18, 6, p)
+    D = orc.dissim(X, [nu], orc.EXACT)[0]
+    _, G = orc.stress(D, Z, nu, latent, orc.EXACT)
+    h = 1e-7
+    for i in range(0, 18, 5):
+        for c in range(p):
+            Zp, Zm = Z.copy(), Z.copy()
+            Zp[i, c] += h
+            Zm[i, c] -= h
+            fd = (orc.stress(D, Zp, nu, latent, orc.EXACT, grad=False)[0]
+                  - orc.stress(D, Zm, nu, latent, orc.EXACT, grad=False)[0]) / (2 * h)
+            assert fd == pytest.approx(G[i, c], rel=1e-5, abs=1e-6)
+
+
+@pytest.mark.parametrize("nu", [1.5, 2.0, 3.0])
+def test_zero_residual_fixed_point(orc, nu):
+    """m == p and Z == X: the latent Gini distances equal Delta, sigma = 0, G = 0."""
+    g = np.random.Generator(np.random.PCG64(55))
+    X = g.standard_normal((20, 3))
+    D = orc.dissim(X, [nu], orc.EXACT)[0]
+    s, G = orc.stress(D, X, nu, orc.LATENT_GINI, orc.EXACT)
+    assert s == 0.0
+    assert np.all(G == 0.0)
+
+
+@pytest.mark.parametrize("latent,p", [(0, 2), (0, 3), (1, 2)])
+def test_gradient_translation_invariance(orc, latent, p):
+    X, Z = _problem(8, 40, 5, p)
+    D = orc.dissim(X, [2.5], orc.EXACT)[0]
+    _, G = orc.stress(D, Z, 2.5, latent, orc.EXACT)
+    assert np.abs(G.sum(axis=0)).max() <= 1e-10 * np.abs(G).sum()
+    if latent == 0:
+        # tie-free Gini weights sum to zero over the coordinates of each point
+        assert np.abs(G.sum(axis=1)).max() <= 1e-10 * np.abs(G).sum()
+
+
+def test_euclid_step_is_guttman_transform(orc):
+    """SMACOF (Section 3.2, unit weights): Z - grad/(2n) = B(Z) Z / n + centroid."""
+    X, Z = _problem(9, 22, 5, 2)
+    n = 22
+    D = orc.dissim(X, [2.0], orc.EXACT)[0]
+    _, G = orc.stress(D, Z, 2.0, orc.LATENT_EUCLID, orc.EXACT)
+    eta = orc.step_size(n, 2, 2.0, orc.LATENT_EUCLID)
+    assert eta == 1.0 / (2 * n)
+    dz = squareform(pdist(Z))
+    B = np.zeros((n, n))
+    off = ~np.eye(n, dtype=bool)
+    B[off] = -D[off] / dz[off]
+    B[np.diag_indices(n)] = -B.sum(axis=1)
+    guttman = B @ Z / n + Z.mean(axis=0)
+    assert np.allclose(Z - eta * G, guttman, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("nu", [1.5, 2.0, 3.0])
+def test_gini_p2_step_constant(orc, nu):
+    n = 50
+    assert orc.step_size(n, 2, nu, orc.LATENT_GINI) == pytest.approx(1.0 / (2 * n * 2 * 4.0 ** (1 - nu)), rel=1e-14)
+
+
+@pytest.mark.parametrize("latent,p,nu", [(1, 2, 2.0), (1, 3, 1.5), (0, 2, 2.0), (0, 2, 3.0), (0, 2, 1.5)])
+def test_monotone_stress(orc, latent, p, nu):
+    from paper_2605_25124_amd import synth
+    w = synth.workload_small()
+    X = w.X[:80]
+    D = orc.dissim(X, [nu], orc.EXACT)[0]
+    Z0 = synth.initial_config(synth.rng_for(1, 1), 80, p, np.float64)
+    _, hist = orc.solve(D, Z0, nu, 60, latent, orc.EXACT)
+    assert hist[-1] < hist[0]
+    assert np.all(np.diff(hist) <= 1e-12 * hist[0])
+
+
+def test_gini_p3_nearly_monotone(orc):
+    from paper_2605_25124_amd import synth
+    w = synth.workload_small()
+    X = w.X[:60]
+    D = orc.dissim(X, [2.0], orc.EXACT)[0]
+    Z0 = synth.initial_config(synth.rng_for(1, 1), 60, 3, np.float64)
+    _, hist = orc.solve(D, Z0, 2.0, 60, orc.LATENT_GINI, orc.EXACT)
+    assert hist[-1] < 0.9 * hist[0]
+    assert np.all(np.diff(hist) <= 1e-5 * hist[0])
+
+
+def test_grad_rows_matches_full_gradient(orc):
+    X, Z = _problem(12, 35, 4, 3)
+    D = orc.dissim(X, [2.0], orc.MATCH32)[0]
+    s, G = orc.stress(D, Z, 2.0, orc.LATENT_GINI, orc.MATCH32)
+    rows = np.array([0, 7, 34])
+    Gr, part = orc.grad_rows(D[rows], rows, Z, 2.0, orc.LATENT_GINI, orc.MATCH32)
+    assert np.allclose(Gr, G[rows], rtol=1e-12, atol=1e-12)
+    allrows = np.arange(35)
+    _, tot = orc.grad_rows(D, allrows, Z, 2.0, orc.LATENT_GINI, orc.MATCH32)
+    assert tot == pytest.approx(s, rel=1e-12)
