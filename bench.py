@@ -1,0 +1,226 @@
+"""Benchmark of the Gini MDS hot path on one MI355X.
+
+A step is one descent iteration of the image workload (n = 10000 points,
+m = 784 coordinates, nu = 2, latent p = 2 with the Gini latent distance):
+the fused stress forward + backward over the upper triangle of Delta with the
+latent re-ranking, the deterministic reduction and the update of Z.  Delta is
+built once before timing (its build time is reported separately), inputs are
+resident in HBM when the timed region starts.
+
+Printed as ONE JSON line:
+  value            pair-evals/s = n(n-1)/2 / seconds per step
+  roofline         the stress-tile kernel: algorithmic bytes per launch
+                   (4 B per pair of the triangle + Z read + G written) over
+                   its average launch time (HIP events on its stream)
+  sweep            the nu-sweep workload (16 problems x 8 nu = 128 instances):
+                   instance-iterations/s of the batched solve vs the plain
+                   one-instance-per-launch path
+  cpu_baseline     the FP64 oracle's stress + gradient on a bounded sample
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "stress fwd+bwd pair-evals/s and HBM GB/s at n=10k; batched vs plain iters/s"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=10000)
+    ap.add_argument("--sweep-iters", type=int, default=200)
+    ap.add_argument("--plain-iters", type=int, default=40)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--mode", choices=["auto", "persistent", "batched"], default="auto")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported (the method's "
+              f"multi-GPU split is described in the design notes, not built)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2605_25124_amd import ginimds as gm
+    from paper_2605_25124_amd import synth
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    pairs = n * (n - 1) // 2
+    w = synth.workload_images(n)
+    X = torch.from_numpy(w.X).to(dev)
+    Z0 = torch.from_numpy(w.Z0[0]).to(dev)
+    p = Z0.shape[1]
+    nu = 2.0
+    torch.cuda.synchronize()
+    log(f"workload {w.name}: {pairs} pairs")
+
+    # ---- Delta, built once (one-off; reported, not part of a step)
+    gm.gini_dissim(X[:256], [nu])                       # warm the library / tables
+    torch.cuda.synchronize()
+    gm.gini_profile_enable(0, True)
+    t0 = time.perf_counter()
+    D = gm.gini_dissim(X, [nu])[0]
+    torch.cuda.synchronize()
+    dissim_s = time.perf_counter() - t0
+    prof = gm.gini_profile_read(0)
+    gm.gini_profile_enable(0, False)
+    log(f"dissim build {dissim_s * 1e3:.1f} ms (kernels {prof['dissim_ms']:.1f} ms)")
+
+    # ---- launch mode for the single large instance
+    def inst(Z, hist=None):
+        return gm.Instance(D, Z, nu, gm.LATENT_GINI, 0.0, hist)
+
+    if args.mode == "auto":
+        best = gm.gini_autotune([inst(Z0.clone())], 3)
+    else:
+        best = {"flags": gm.SOLVE_PERSISTENT if args.mode == "persistent" else gm.SOLVE_BATCHED,
+                "tile": 256, "grid": 0}
+    mode_name = "persistent" if best["flags"] == gm.SOLVE_PERSISTENT else "batched"
+    log(f"mode {mode_name} tile {best['tile']} grid {best['grid']}")
+
+    Zw = Z0.clone()
+    gm.gini_mds_solve([inst(Zw)], args.warmup, best["flags"], best["tile"], best["grid"])
+    torch.cuda.synchronize()
+
+    # ---- timed region: K descent steps
+    Z = Z0.clone()
+    hist = torch.zeros(args.steps, device=dev)
+    gm.gini_profile_enable(0, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gm.gini_mds_solve([inst(Z, hist)], args.steps, best["flags"], best["tile"], best["grid"])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = gm.gini_profile_read(0)
+    gm.gini_profile_enable(0, False)
+    ms_step = el * 1e3 / args.steps
+    value = pairs / (el / args.steps)
+    h = hist.cpu().numpy()
+    log(f"{args.steps} steps: {ms_step * 1e3:.1f} us/step, sigma {h[0]:.6e} -> {h[-1]:.6e}")
+
+    # dominant kernel and its algorithmic traffic per launch
+    alg_bytes = 4.0 * pairs + 4.0 * n * p + 4.0 * n * p
+    if prof["tile_launches"] > 0:
+        kname = "k_stress_tiles"
+        launches = prof["tile_launches"]
+        avg_ms = prof["tile_ms"] / launches
+    else:
+        kname = "k_solve_persistent"
+        launches = args.steps                      # one launch covers every step
+        avg_ms = prof["persistent_ms"] / max(args.steps, 1)
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,
+            "avg_launch_us": round(avg_ms * 1e3, 2), "alg_bytes_per_launch": alg_bytes,
+            "reduce_avg_us": round(prof["reduce_ms"] * 1e3 / max(prof["reduce_launches"], 1), 2)}
+    log(f"roofline {kname}: {avg_ms * 1e3:.1f} us/launch -> {achieved:.0f} GB/s")
+
+    # ---- nu-sweep: batched persistent vs plain
+    sweep = None
+    if not args.no_sweep:
+        del D
+        torch.cuda.empty_cache()
+        probs = synth.workload_sweep()
+        Ds, Z0s, nus = [], [], []
+        t0 = time.perf_counter()
+        for pr in probs:
+            Dk = gm.gini_dissim(torch.from_numpy(pr.X).to(dev), pr.nus)
+            for k, nuk in enumerate(pr.nus):
+                Ds.append(Dk[k])
+                Z0s.append(torch.from_numpy(pr.Z0[k]).to(dev))
+                nus.append(nuk)
+        torch.cuda.synchronize()
+        sweep_build = time.perf_counter() - t0
+        n_inst = len(Ds)
+
+        def insts():
+            return [gm.Instance(Ds[k], Z0s[k].clone(), nus[k]) for k in range(n_inst)]
+
+        tuned = gm.gini_autotune(insts(), 3)
+        log(f"sweep: {n_inst} instances, build {sweep_build:.2f} s, tuned {tuned}")
+        I1 = insts()
+        gm.gini_mds_solve(I1, 5, tuned["flags"], tuned["tile"], tuned["grid"])
+        I1 = insts()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gm.gini_mds_solve(I1, args.sweep_iters, tuned["flags"], tuned["tile"], tuned["grid"])
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        batched_rate = n_inst * args.sweep_iters / tb
+        I2 = insts()
+        gm.gini_mds_solve(I2, 2, gm.SOLVE_PLAIN, tuned["tile"])
+        I2 = insts()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gm.gini_mds_solve(I2, args.plain_iters, gm.SOLVE_PLAIN, tuned["tile"])
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        plain_rate = n_inst * args.plain_iters / tp
+        sweep = {"workload": "16 Gaussian-mixture problems n~U{100..3000} m~U{4..64} x 8 nu in [1.1,4], p=2",
+                 "instances": n_inst, "batched_mode": "persistent" if tuned["flags"] == gm.SOLVE_PERSISTENT
+                 else "batched", "tile": tuned["tile"], "grid": tuned["grid"],
+                 "batched_iters_per_s": round(batched_rate, 1), "plain_iters_per_s": round(plain_rate, 1),
+                 "speedup": round(batched_rate / plain_rate, 2), "batched_iters": args.sweep_iters,
+                 "plain_iters": args.plain_iters, "dissim_build_s": round(sweep_build, 3)}
+        log(f"sweep batched {batched_rate:.0f} it/s, plain {plain_rate:.0f} it/s, x{batched_rate / plain_rate:.2f}")
+
+    # ---- CPU baseline: the oracle as it stands, bounded sample
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        from scipy.spatial.distance import pdist, squareform
+        ns = 3000
+        # stand-in dissimilarities for the sample (their values do not change
+        # the oracle's cost): scaled L1 distances of the same rows
+        Ds_ = squareform(pdist(w.X[:ns].astype(np.float64), "cityblock")) / 784.0
+        Zs = w.Z0[0][:ns].astype(np.float64)
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            Zs, _ = O.solve(Ds_, Zs, nu, 1, O.LATENT_GINI, O.MATCH32)   # stress + gradient + step
+            reps += 1
+            if time.perf_counter() - t0 >= args.cpu_seconds:
+                break
+        el_c = time.perf_counter() - t0
+        cpu = {"value": round(reps * ns * (ns - 1) / 2 / el_c, 1), "unit": "pair-evals/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"oracle descent step (stress + gradient + update, FP64, one thread) on the first "
+                         f"{ns} points of the image workload (p=2 Gini latent), {reps} steps in {el_c:.1f} s"}
+        log(f"cpu oracle {cpu['value']:.3e} pair-evals/s")
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "pair-evals/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"images n={n} m=784 (28x28 blobs, uint8 + N(0,32^2) noise), nu=2, "
+                                  f"p=2 Gini latent, raw stress, fixed-step descent",
+                      "n": n, "m": 784, "p": p, "nu": nu, "mode": mode_name, "tile": best["tile"],
+                      "parallelism": "single GPU"},
+           "hbm_gbs_algorithmic": round(achieved, 1),
+           "dissim_build_s": round(dissim_s, 4),
+           "roofline": roof, "sweep": sweep, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

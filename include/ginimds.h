@@ -1,0 +1,238 @@
+/*
+ * ginimds.h -- C ABI of the Gini MDS library for AMD MI355X (gfx950).
+ *
+ * The library computes, on one GPU, the data-parallel hot path of Gini
+ * multidimensional scaling (arXiv 2605.25124):
+ *   - the doubled midranks of the coordinates of a vector (Definition 1 with
+ *     the tie rule of Section 2.1),
+ *   - the matrix of generalised Gini pseudo-distances between all pairs of
+ *     rows of a data matrix (Section 2.2; the "compute Gini pseudo-distances"
+ *     step of Algorithm 1),
+ *   - the raw stress of a latent configuration against that matrix and its
+ *     gradient (the SMACOF loss of Section 3.2 with unit weights), with the
+ *     latent coordinates re-ranked at every evaluation,
+ *   - fixed-step gradient-descent fits of many such problems, including a
+ *     sweep over nu (Algorithm 1), in one persistent launch.
+ *
+ * Conventions shared by every entry point:
+ *   - Array arguments are DEVICE pointers on the context's device unless the
+ *     comment says "host".  Matrices are row-major with an explicit leading
+ *     dimension (elements between the starts of consecutive rows).
+ *   - Calls are asynchronous on the given stream and return once the work is
+ *     enqueued, except gini_mds_solve and gini_autotune, which synchronise the
+ *     stream before returning (see there).  A NULL stream is the null stream.
+ *   - Inputs must be finite.  Ranks compare FP32 values with IEEE < and ==, so
+ *     -0 and +0 tie.
+ *   - The caller owns every array it passes.  The context owns its scratch
+ *     memory and weight tables; it grows scratch on demand, outside any
+ *     kernel, and frees everything in gini_destroy.
+ *   - Errors: arguments are validated on the host before any GPU work is
+ *     enqueued; a failed check returns GINI_EINVAL (or GINI_EUNSUPPORTED) and
+ *     enqueues nothing.  gini_last_error(ctx) then describes the failure.
+ *     A HIP runtime failure returns GINI_EDEVICE.
+ *   - One context serves one host thread at a time.  Calls on two streams of
+ *     one context share its scratch and must not overlap.
+ */
+#ifndef GINIMDS_H
+#define GINIMDS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Opaque HIP stream handle (the same pointer type as hipStream_t). */
+typedef struct ihipStream_t* gini_stream_t;
+
+typedef enum {
+    GINI_OK = 0,
+    GINI_EINVAL = 1,        /* an argument failed validation                 */
+    GINI_ENOMEM = 2,        /* device or host allocation failed              */
+    GINI_EDEVICE = 3,       /* HIP runtime error, or a device-side failure   */
+    GINI_ENOTFINITE = 4,    /* a result was not finite (checked solves only) */
+    GINI_EUNSUPPORTED = 5   /* valid but outside what this build supports    */
+} gini_status;
+
+/* Distance used between latent points.  GINI: the generalised Gini
+ * pseudo-distance of Section 2.2 over the p latent coordinates (the latent
+ * space is a Gini metric space, Section 3.2).  EUCLID: the Euclidean norm
+ * used by Algorithm 1 to evaluate the Kruskal stress. */
+typedef enum { GINI_LATENT_GINI = 0, GINI_LATENT_EUCLID = 1 } gini_latent;
+
+typedef struct gini_ctx gini_ctx;
+
+/* Create a context bound to HIP device `device` (>= 0).  No HIP call is made
+ * until the first entry point that enqueues work. */
+gini_status gini_create(gini_ctx** ctx, int device);
+/* Free the context and everything it owns; NULL is a no-op.  Waits for the
+ * context's device to finish its outstanding work first. */
+void gini_destroy(gini_ctx* ctx);
+/* Description of the last failure on this context ("" if none).  The string
+ * stays valid until the next call on the context. */
+const char* gini_last_error(const gini_ctx* ctx);
+/* Static name of a status code. */
+const char* gini_status_string(gini_status s);
+/* Library version, major*10000 + minor*100 + patch. */
+int gini_version(void);
+
+/*
+ * gini_weight_table -- host-side table used by every kernel: the weight a
+ * coordinate of doubled midrank t receives in the symmetrised generalised
+ * Gini pseudo-distance of d-vectors (Section 2.2, with the survival function
+ * of a coordinate taken as 1 - R/d):
+ *     W[t-2] = ((t-2)/(2d))^(nu-1) - ((2d-t)/(2d))^(nu-1),  t = 2 .. 2d,
+ * computed in FP64 and rounded once to FP32; exactly antisymmetric,
+ * W[2d+2-t] == -W[t].  W: HOST array of 2d-1 floats.  1 <= d <= 65536,
+ * nu finite and > 1.  Makes no HIP call; ctx is not needed.
+ */
+gini_status gini_weight_table(int32_t d, double nu, float* W);
+
+/*
+ * gini_rank -- doubled midranks of every row of V (Definition 1; ties share
+ * the mean of the ranks they occupy, the rule of Section 2.1, so that the zero
+ * vector has R = (d+1)/2 everywhere):
+ *     twoR[r*ldr + c] = 2*#{c' : V[r,c'] < V[r,c]} + #{c' : V[r,c'] == V[r,c]} + 1
+ * V: rows x d FP32, leading dimension ldv >= d.  twoR: rows x d int32,
+ * leading dimension ldr >= d.  rows == 0 is a no-op.  1 <= d <= 2^20.
+ * Bit-exact: integer result of FP32 comparisons.
+ */
+gini_status gini_rank(gini_ctx* ctx, const float* V, int64_t rows, int32_t d, int64_t ldv,
+                      int32_t* twoR, int64_t ldr, gini_stream_t stream);
+
+/*
+ * gini_dissim -- generalised Gini pseudo-distance between every pair of rows
+ * of X (Section 2.2, symmetrised form), for each nu in a list, from one
+ * ranking of each pair's difference vector:
+ *     Delta_k[i, j] = (m/2) * sum_c z_c * W_{m,nu_k}[t_c],   z = fl32(X_i - X_j),
+ *     t = doubled midranks of z,
+ *     W_{m,nu}[t] = ((t-2)/(2m))^(nu-1) - ((2m-t)/(2m))^(nu-1)
+ * which is half the distance from x to y plus half the distance from y to x
+ * with the survival function of a coordinate of z taken as 1 - R/m.
+ * X: n x m FP32 (ldx >= m).  nu: HOST array of n_nu values, each finite and
+ * > 1 (1 <= n_nu <= 64).  Delta: n_nu matrices n x n FP32 (ldd >= n), matrix
+ * k starting at Delta + k*stride_nu (stride_nu >= n*ldd when n_nu > 1).
+ * The full symmetric matrices are written, with an exact zero diagonal;
+ * Delta[j,i] is bitwise equal to Delta[i,j].  n >= 1, 1 <= m <= 4096.
+ * FP32 arithmetic with per-lane partial sums; error against an FP64
+ * evaluation on the same FP32 differences is below 1e-5 of
+ * (m/2)*sum_c |z_c W[t_c]|.
+ */
+gini_status gini_dissim(gini_ctx* ctx, const float* X, int64_t n, int32_t m, int64_t ldx,
+                        const double* nu, int32_t n_nu, float* Delta, int64_t ldd,
+                        int64_t stride_nu, gini_stream_t stream);
+
+/*
+ * gini_stress_fwd -- raw stress of the configuration Z against Delta (the
+ * SMACOF loss of Section 3.2 with unit weights, pairs i < j):
+ *     sigma = sum_{i<j} (delta(Z_i - Z_j) - Delta[i,j])^2
+ * where delta is the latent distance (gini_latent): for GINI the Gini
+ * pseudo-distance of the p latent coordinates at the given nu, re-ranked for
+ * every pair; for EUCLID the Euclidean norm.  Only the strict upper triangle
+ * of Delta is read.
+ * Delta: n x n FP32 (ldd >= n).  Z: n x p FP32 (ldz >= p), 1 <= p <= 8
+ * (GINI needs p >= 2: the distance of a 1-vector is identically zero).
+ * out_sigma: device float[2] receiving (hi, lo), sigma = hi + lo.  n >= 2.
+ */
+gini_status gini_stress_fwd(gini_ctx* ctx, const float* Delta, int64_t n, int64_t ldd,
+                            const float* Z, int32_t p, int64_t ldz, double nu, gini_latent latent,
+                            float* out_sigma, gini_stream_t stream);
+
+/*
+ * gini_stress_bwd -- the same stress and its gradient in ONE pass over Delta:
+ *     gradZ[i,:] = scale * d sigma / d Z_i
+ *                = scale * sum_{j != i} 2 (delta_ij - Delta_ij) * d delta(Z_i - Z_j) / d Z_i
+ * with the latent ranks held fixed (the distance is piecewise linear, so this
+ * is its gradient almost everywhere and a subgradient at ties).
+ * grad_out: device float scalar multiplying the gradient, or NULL for 1.
+ * gradZ: n x p FP32 (ldg >= p), fully overwritten.  out_sigma: as in
+ * gini_stress_fwd, or NULL.  Deterministic: fixed reduction order, no
+ * floating-point atomics, so repeated calls are bitwise identical.
+ */
+gini_status gini_stress_bwd(gini_ctx* ctx, const float* Delta, int64_t n, int64_t ldd,
+                            const float* Z, int32_t p, int64_t ldz, double nu, gini_latent latent,
+                            const float* grad_out, float* gradZ, int64_t ldg, float* out_sigma,
+                            gini_stream_t stream);
+
+/* One MDS instance for gini_mds_solve (all pointers are device pointers). */
+typedef struct {
+    int64_t n;             /* points, >= 2                                     */
+    int32_t p;             /* latent dimension, 1..8 (>= 2 for GINI)           */
+    int32_t reserved0;     /* must be 0                                        */
+    const float* Delta;    /* n x n dissimilarities (upper triangle read)      */
+    int64_t ldd;           /* >= n                                             */
+    float* Z;              /* n x p configuration, updated in place            */
+    int64_t ldz;           /* >= p                                             */
+    double nu;             /* > 1, used by the GINI latent distance            */
+    gini_latent latent;
+    float eta;             /* step; <= 0 selects 1 / (2 n c) (see below)       */
+    float* sigma_hist;     /* iters floats: sigma(Z_t) before step t; or NULL  */
+} gini_instance;
+
+enum {
+    GINI_SOLVE_PERSISTENT = 1,   /* all instances, all iterations, one launch   */
+    GINI_SOLVE_PLAIN = 2,        /* per instance, per iteration: 2 launches     */
+    GINI_SOLVE_BATCHED = 4,      /* per iteration: 2 launches for all instances */
+    GINI_SOLVE_AUTOTUNE = 8,     /* choose tile, grid and mode by measurement   */
+    GINI_SOLVE_CHECK_FINITE = 16 /* return GINI_ENOTFINITE if a sigma is not    */
+};
+
+typedef struct {
+    int32_t iters;     /* >= 0                                                  */
+    int32_t flags;     /* one of PERSISTENT / PLAIN / BATCHED, or AUTOTUNE;
+                          plus CHECK_FINITE                                     */
+    int32_t tile;      /* 0 = library choice, else 64, 128 or 256               */
+    int32_t grid;      /* persistent workgroups; 0 = library choice             */
+} gini_solve_opts;
+
+/*
+ * gini_mds_solve -- "Run MDS" of Algorithm 1: for every instance, iters
+ * fixed steps of gradient descent on the raw stress,
+ *     sigma_hist[t] = sigma(Z_t),   Z_{t+1} = Z_t - eta * grad sigma(Z_t),
+ * with default eta = 1 / (2 n c), c = |d delta / d u|^2 at a tie-free u
+ * (c = 1 for EUCLID, where the step is the Guttman transform of SMACOF plus
+ * a translation; c = 2 * 4^(1-nu) for GINI at p = 2).
+ * inst: HOST array of n_inst descriptors (1 <= n_inst <= 65536).  Instances
+ * must not share Z or sigma_hist.  The three modes give bitwise identical
+ * results for the same tile size.  Synchronises `stream` before returning
+ * (to report device-side failures); a persistent launch that stops making
+ * progress aborts and returns GINI_EDEVICE.
+ */
+gini_status gini_mds_solve(gini_ctx* ctx, const gini_instance* inst, int32_t n_inst,
+                           const gini_solve_opts* opts, gini_stream_t stream);
+
+/*
+ * gini_autotune -- time candidate (mode, tile, grid) choices for this batch of
+ * instances over `probe_iters` iterations each, on copies of the
+ * configurations (the caller's Z and histories are not modified), and write
+ * the fastest into *best (flags keep the caller's CHECK_FINITE bit).  The
+ * result is cached in the context, keyed by the batch's shape, and used by
+ * gini_mds_solve with GINI_SOLVE_AUTOTUNE.  Synchronises `stream`.
+ */
+gini_status gini_autotune(gini_ctx* ctx, const gini_instance* inst, int32_t n_inst,
+                          int32_t probe_iters, gini_solve_opts* best, gini_stream_t stream);
+
+/* Kernel timing collected by the context while profiling is enabled: HIP
+ * events recorded on the launching stream around each stress-tile launch,
+ * each reduction launch and each persistent launch. */
+typedef struct {
+    int64_t tile_launches;
+    double tile_ms;          /* summed durations of the stress-tile kernels */
+    int64_t reduce_launches;
+    double reduce_ms;
+    int64_t persistent_launches;
+    double persistent_ms;
+    int64_t dissim_launches;
+    double dissim_ms;
+} gini_profile;
+
+/* Start (enable != 0) or stop recording kernel timings; clears the totals. */
+gini_status gini_profile_enable(gini_ctx* ctx, int enable);
+/* Wait for the recorded events, return the totals and clear them. */
+gini_status gini_profile_read(gini_ctx* ctx, gini_profile* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GINIMDS_H */

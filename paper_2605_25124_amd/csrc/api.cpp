@@ -1,0 +1,886 @@
+// api.cpp -- host runtime behind the C ABI of include/ginimds.h: contexts,
+// argument validation, Gini weight tables, scratch management, descriptor
+// upload, launch selection and the autotuner.  Every numeric step runs in the
+// HIP kernels; the host only prepares tables of the weight function and
+// decides what to launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/ginimds.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+using gmds::InstDesc;
+
+namespace {
+
+constexpr int kVersion = 10000;     // 1.0.0
+constexpr int kRing = 16;           // descriptor upload slots
+constexpr int64_t kMaxRankD = 1 << 20;
+constexpr int kMaxDissimM = 4096;
+
+struct Slot {
+    void* host = nullptr;   // pinned
+    void* dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool used = false;
+};
+
+struct TableKey {
+    int d;
+    std::vector<double> nus;
+    bool operator<(const TableKey& o) const {
+        if (d != o.d) return d < o.d;
+        return nus < o.nus;
+    }
+};
+
+struct TuneEntry {
+    gini_solve_opts opts;
+};
+
+}  // namespace
+
+struct gini_ctx {
+    int device = 0;
+    bool ready = false;
+    int cus = 0;
+    std::string err;
+    // scratch for tile partials (grown on demand)
+    float* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    // persistent-solve control
+    gmds::SolveCtl* ctl = nullptr;
+    uint32_t* counters = nullptr;
+    uint32_t* epochs = nullptr;
+    size_t ctl_cap = 0;      // instances
+    Slot ring[kRing];
+    int ring_next = 0;
+    std::map<TableKey, float*> tables;
+    std::map<std::string, TuneEntry> tune;
+    // kernel timing (gini_profile_enable)
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[4];   // tile, reduce, persistent, dissim
+    std::vector<hipEvent_t> ev_pool;
+    int64_t spin_limit = 1000000000;   // ticks of the constant-rate device clock
+    bool spin_override = false;
+};
+
+namespace {
+
+gini_status fail(gini_ctx* c, gini_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return s;
+}
+
+gini_status hip_fail(gini_ctx* c, hipError_t e, const char* where) {
+    return fail(c, GINI_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define GINI_HIP(ctx, call)                                           \
+    do {                                                              \
+        hipError_t e_ = (call);                                       \
+        if (e_ != hipSuccess) return hip_fail((ctx), e_, #call);      \
+    } while (0)
+
+gini_status ensure_ready(gini_ctx* c) {
+    if (c->ready) {
+        GINI_HIP(c, hipSetDevice(c->device));
+        return GINI_OK;
+    }
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) return fail(c, GINI_EDEVICE, "no HIP device available");
+    if (c->device >= count) return fail(c, GINI_EINVAL, "device %d out of range (%d devices)", c->device, count);
+    GINI_HIP(c, hipSetDevice(c->device));
+    hipDeviceProp_t prop;
+    GINI_HIP(c, hipGetDeviceProperties(&prop, c->device));
+    c->cus = prop.multiProcessorCount;
+    // the persistent solver's wait limit is counted in ticks of the device's
+    // constant-rate clock: 10 s unless GINI_SPIN_LIMIT_TICKS overrides it
+    int khz = 0;
+    if (!c->spin_override && hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) == hipSuccess &&
+        khz > 0)
+        c->spin_limit = (int64_t)khz * 1000 * 10;
+    for (int i = 0; i < kRing; ++i) GINI_HIP(c, hipEventCreateWithFlags(&c->ring[i].done, hipEventDisableTiming));
+    c->ready = true;
+    return GINI_OK;
+}
+
+// Copy `bytes` from host to a device staging slot on `s`; returns the device
+// pointer.  The slot is reused only after the work recorded on it has ended.
+gini_status upload(gini_ctx* c, const void* src, size_t bytes, hipStream_t s, void** dev, Slot** slot_out) {
+    Slot& sl = c->ring[c->ring_next];
+    c->ring_next = (c->ring_next + 1) % kRing;
+    if (sl.used) GINI_HIP(c, hipEventSynchronize(sl.done));
+    if (sl.cap < bytes) {
+        if (sl.host) GINI_HIP(c, hipHostFree(sl.host));
+        if (sl.dev) GINI_HIP(c, hipFree(sl.dev));
+        sl.host = sl.dev = nullptr;
+        size_t cap = std::max<size_t>(bytes, 4096);
+        if (hipHostMalloc(&sl.host, cap, hipHostMallocDefault) != hipSuccess)
+            return fail(c, GINI_ENOMEM, "pinned staging allocation of %zu bytes failed", cap);
+        if (hipMalloc(&sl.dev, cap) != hipSuccess) return fail(c, GINI_ENOMEM, "device staging allocation failed");
+        sl.cap = cap;
+    }
+    std::memcpy(sl.host, src, bytes);
+    GINI_HIP(c, hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, s));
+    *dev = sl.dev;
+    *slot_out = &sl;
+    return GINI_OK;
+}
+
+gini_status slot_done(gini_ctx* c, Slot* sl, hipStream_t s) {
+    GINI_HIP(c, hipEventRecord(sl->done, s));
+    sl->used = true;
+    return GINI_OK;
+}
+
+enum { kProfTile = 0, kProfReduce = 1, kProfPersistent = 2, kProfDissim = 3 };
+
+hipEvent_t pool_event(gini_ctx* c) {
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void prof_clear(gini_ctx* c) {
+    for (auto& v : c->prof_ev) {
+        for (auto& pr : v) {
+            c->ev_pool.push_back(pr.first);
+            c->ev_pool.push_back(pr.second);
+        }
+        v.clear();
+    }
+}
+
+// Brackets one launch with events when profiling is on.
+struct ProfScope {
+    gini_ctx* c;
+    int kind;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    ProfScope(gini_ctx* c_, int kind_, hipStream_t s_) : c(c_), kind(kind_), s(s_) {
+        if (c->prof) {
+            a = pool_event(c);
+            if (a) (void)hipEventRecord(a, s);
+        }
+    }
+    ~ProfScope() {
+        if (!a) return;
+        hipEvent_t b = pool_event(c);
+        if (!b) return;
+        (void)hipEventRecord(b, s);
+        c->prof_ev[kind].emplace_back(a, b);
+    }
+};
+
+gini_status ensure_scratch(gini_ctx* c, size_t bytes) {
+    if (bytes <= c->scratch_bytes) return GINI_OK;
+    if (c->scratch) {
+        GINI_HIP(c, hipDeviceSynchronize());
+        GINI_HIP(c, hipFree(c->scratch));
+        c->scratch = nullptr;
+        c->scratch_bytes = 0;
+    }
+    size_t cap = std::max(bytes, c->scratch_bytes * 3 / 2);
+    cap = (cap + 255) & ~size_t(255);
+    if (hipMalloc(reinterpret_cast<void**>(&c->scratch), cap) != hipSuccess)
+        return fail(c, GINI_ENOMEM, "scratch allocation of %zu bytes failed", cap);
+    c->scratch_bytes = cap;
+    return GINI_OK;
+}
+
+gini_status ensure_ctl(gini_ctx* c, size_t n_inst) {
+    if (n_inst <= c->ctl_cap && c->ctl) return GINI_OK;
+    if (c->ctl) {
+        GINI_HIP(c, hipDeviceSynchronize());
+        (void)hipFree(c->ctl);
+        (void)hipFree(c->counters);
+        (void)hipFree(c->epochs);
+        c->ctl = nullptr;
+    }
+    size_t cap = std::max<size_t>(n_inst, 64);
+    if (hipMalloc(reinterpret_cast<void**>(&c->ctl), sizeof(gmds::SolveCtl)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&c->counters), cap * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&c->epochs), cap * sizeof(uint32_t)) != hipSuccess)
+        return fail(c, GINI_ENOMEM, "solve control allocation failed");
+    c->ctl_cap = cap;
+    return GINI_OK;
+}
+
+// W_{d,nu}[t] for t = 2..2d (index t-2): ((t-2)/(2d))^(nu-1) - ((2d-t)/(2d))^(nu-1),
+// the weight a coordinate of doubled midrank t receives in the symmetrised
+// generalised Gini pseudo-distance.  Built in FP64 as A[t] - A[2d+2-t] so that
+// the FP32 table is exactly antisymmetric, W[2d+2-t] == -W[t].
+void weight_table(int d, double nu, double* out) {
+    const int len = 2 * d - 1;
+    std::vector<double> A(len);
+    for (int t = 2; t <= 2 * d; ++t) A[t - 2] = std::pow((double)(t - 2) / (2.0 * d), nu - 1.0);
+    for (int t = 2; t <= 2 * d; ++t) out[t - 2] = A[t - 2] - A[2 * d - t];
+}
+
+gini_status get_tables(gini_ctx* c, int d, const double* nu, int n_nu, hipStream_t s, float** dev) {
+    TableKey key{d, std::vector<double>(nu, nu + n_nu)};
+    auto it = c->tables.find(key);
+    if (it != c->tables.end()) {
+        *dev = it->second;
+        return GINI_OK;
+    }
+    const int len = 2 * d - 1;
+    std::vector<float> host((size_t)len * n_nu);
+    std::vector<double> w(len);
+    for (int k = 0; k < n_nu; ++k) {
+        weight_table(d, nu[k], w.data());
+        for (int i = 0; i < len; ++i) host[(size_t)k * len + i] = (float)w[i];
+    }
+    float* p = nullptr;
+    if (hipMalloc(reinterpret_cast<void**>(&p), host.size() * sizeof(float)) != hipSuccess)
+        return fail(c, GINI_ENOMEM, "weight table allocation failed");
+    GINI_HIP(c, hipMemcpy(p, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice));
+    c->tables[key] = p;
+    *dev = p;
+    (void)s;
+    return GINI_OK;
+}
+
+bool bad_nu(double nu) { return !std::isfinite(nu) || !(nu > 1.0); }
+
+gini_status check_latent(gini_ctx* c, int32_t p, double nu, int latent) {
+    if (latent != GINI_LATENT_GINI && latent != GINI_LATENT_EUCLID)
+        return fail(c, GINI_EINVAL, "latent must be GINI_LATENT_GINI or GINI_LATENT_EUCLID");
+    if (p < 1 || p > gmds::kMaxP) return fail(c, GINI_EINVAL, "p = %d outside 1..%d", p, gmds::kMaxP);
+    if (latent == GINI_LATENT_GINI && p < 2)
+        return fail(c, GINI_EINVAL, "the Gini latent distance needs p >= 2 (it is identically 0 for p = 1)");
+    if (latent == GINI_LATENT_GINI && bad_nu(nu)) return fail(c, GINI_EINVAL, "nu must be finite and > 1");
+    return GINI_OK;
+}
+
+// Latent-space constants: (p/2) W_{p,nu}[t] and the default step factor
+// c = |d delta / d u|^2 at a tie-free u.
+void latent_consts(int p, double nu, int latent, InstDesc& D, double& c) {
+    for (int i = 0; i < 2 * gmds::kMaxP - 1; ++i) D.wtab[i] = 0.f;
+    D.c2 = 0.f;
+    c = 1.0;
+    if (latent == GINI_LATENT_GINI) {
+        std::vector<double> w(2 * p - 1);
+        weight_table(p, nu, w.data());
+        for (int i = 0; i < 2 * p - 1; ++i) D.wtab[i] = (float)(0.5 * p * w[i]);
+        if (p == 2) D.c2 = D.wtab[2];
+        c = 0.0;
+        for (int k = 1; k <= p; ++k) {
+            const double a = 0.5 * p * w[2 * k - 2];
+            c += a * a;
+        }
+    }
+}
+
+int pick_tile(int64_t n) {
+    if (n <= 512) return 64;
+    if (n <= 4096) return 128;
+    return 256;
+}
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// Fill the layout fields of one stress descriptor for tile size T; returns tiles.
+int64_t layout(InstDesc& D, int T) {
+    D.nb = cdiv(D.n, T);
+    D.vec = (aligned16(D.Delta) && (D.ldd % 4) == 0) ? 1 : 0;
+    return gmds::tri_count(D.nb);
+}
+
+size_t partial_floats(const InstDesc& D, int T, int pg) {
+    const int64_t nt = gmds::tri_count(D.nb);
+    return (size_t)nt * T * pg * 2 + (size_t)nt * 2;
+}
+
+void assign_partials(InstDesc& D, float* base, int T, int pg) {
+    const int64_t nt = gmds::tri_count(D.nb);
+    D.rowpart = base;
+    D.colpart = base + (size_t)nt * T * pg;
+    D.sigpart = base + (size_t)nt * T * pg * 2;
+}
+
+gini_status stress_common(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, const float* Z, int32_t p,
+                          int64_t ldz, double nu, gini_latent latent, const float* grad_out, float* gradZ,
+                          int64_t ldg, float* out_sigma, bool grad, hipStream_t s) {
+    if (!c) return GINI_EINVAL;
+    c->err.clear();
+    if (!Delta || !Z) return fail(c, GINI_EINVAL, "Delta and Z must be non-null");
+    if (n < 2) return fail(c, GINI_EINVAL, "n = %lld: need at least two points", (long long)n);
+    if (ldd < n) return fail(c, GINI_EINVAL, "ldd = %lld < n = %lld", (long long)ldd, (long long)n);
+    gini_status st = check_latent(c, p, nu, latent);
+    if (st != GINI_OK) return st;
+    if (ldz < p) return fail(c, GINI_EINVAL, "ldz = %lld < p = %d", (long long)ldz, p);
+    if (grad) {
+        if (!gradZ) return fail(c, GINI_EINVAL, "gradZ must be non-null");
+        if (ldg < p) return fail(c, GINI_EINVAL, "ldg = %lld < p = %d", (long long)ldg, p);
+    } else if (!out_sigma) {
+        return fail(c, GINI_EINVAL, "out_sigma must be non-null");
+    }
+    if ((uint64_t)n > (uint64_t)1 << 31) return fail(c, GINI_EUNSUPPORTED, "n > 2^31 is not supported");
+    st = ensure_ready(c);
+    if (st != GINI_OK) return st;
+    const int T = pick_tile(n);
+    InstDesc D{};
+    D.Delta = Delta;
+    D.Z = const_cast<float*>(Z);
+    D.gradZ = gradZ;
+    D.grad_out = grad_out;
+    D.out_sigma = out_sigma;
+    D.n = n;
+    D.ldd = ldd;
+    D.ldz = ldz;
+    D.ldg = ldg;
+    D.p = p;
+    double cc;
+    latent_consts(p, nu, latent, D, cc);
+    const int64_t nt = layout(D, T);
+    if (nt > (int64_t)0x7fffffff) return fail(c, GINI_EUNSUPPORTED, "too many tiles");
+    const int pg = gmds::stored_components(p, latent);
+    st = ensure_scratch(c, partial_floats(D, T, pg) * sizeof(float));
+    if (st != GINI_OK) return st;
+    assign_partials(D, c->scratch, T, pg);
+    D.tile_off = 0;
+    void* dd = nullptr;
+    Slot* sl = nullptr;
+    st = upload(c, &D, sizeof D, s, &dd, &sl);
+    if (st != GINI_OK) return st;
+    const InstDesc* ddp = static_cast<const InstDesc*>(dd);
+    {
+        ProfScope ps(c, kProfTile, s);
+        GINI_HIP(c, gmds::launch_stress_tiles(ddp, 1, nt, 0, p, latent, T, grad, s));
+    }
+    {
+        ProfScope ps(c, kProfReduce, s);
+        GINI_HIP(c, gmds::launch_stress_reduce(ddp, &D, 1, p, latent, T, grad ? 0 : 2, 0, s));
+    }
+    return slot_done(c, sl, s);
+}
+
+// ------------------------------------------------------------------ solve
+struct Plan {
+    std::vector<InstDesc> desc;     // in queue (LPT) order
+    std::vector<int> order;         // desc[k] is caller instance order[k]
+    std::vector<int64_t> prefix;    // tile prefix, n_inst + 1
+    int64_t tiles = 0;
+    int p = 0, latent = 0, T = 0;
+};
+
+gini_status validate_instances(gini_ctx* c, const gini_instance* inst, int32_t n_inst) {
+    if (!inst) return fail(c, GINI_EINVAL, "inst must be non-null");
+    if (n_inst < 1 || n_inst > 65536) return fail(c, GINI_EINVAL, "n_inst = %d outside 1..65536", n_inst);
+    for (int k = 0; k < n_inst; ++k) {
+        const gini_instance& I = inst[k];
+        if (!I.Delta || !I.Z) return fail(c, GINI_EINVAL, "instance %d: Delta and Z must be non-null", k);
+        if (I.n < 2) return fail(c, GINI_EINVAL, "instance %d: n = %lld < 2", k, (long long)I.n);
+        if ((uint64_t)I.n > (uint64_t)1 << 31) return fail(c, GINI_EUNSUPPORTED, "instance %d: n too large", k);
+        if (I.ldd < I.n) return fail(c, GINI_EINVAL, "instance %d: ldd < n", k);
+        if (I.ldz < I.p) return fail(c, GINI_EINVAL, "instance %d: ldz < p", k);
+        if (I.reserved0 != 0) return fail(c, GINI_EINVAL, "instance %d: reserved0 must be 0", k);
+        if (!std::isfinite(I.eta)) return fail(c, GINI_EINVAL, "instance %d: eta not finite", k);
+        gini_status st = check_latent(c, I.p, I.nu, I.latent);
+        if (st != GINI_OK) return fail(c, st, "instance %d: %s", k, c->err.c_str());
+        if (I.p != inst[0].p || I.latent != inst[0].latent)
+            return fail(c, GINI_EUNSUPPORTED, "instance %d: all instances of one call must share p and latent", k);
+    }
+    for (int k = 0; k < n_inst; ++k)
+        for (int l = k + 1; l < n_inst && n_inst <= 4096; ++l) {
+            if (inst[k].Z == inst[l].Z) return fail(c, GINI_EINVAL, "instances %d and %d share Z", k, l);
+            if (inst[k].sigma_hist && inst[k].sigma_hist == inst[l].sigma_hist)
+                return fail(c, GINI_EINVAL, "instances %d and %d share sigma_hist", k, l);
+        }
+    return GINI_OK;
+}
+
+gini_status make_plan(gini_ctx* c, const gini_instance* inst, int32_t n_inst, int T, Plan& P) {
+    P.p = inst[0].p;
+    P.latent = inst[0].latent;
+    P.T = T;
+    P.order.resize(n_inst);
+    std::iota(P.order.begin(), P.order.end(), 0);
+    // largest first (LPT), ties by caller order
+    std::stable_sort(P.order.begin(), P.order.end(), [&](int a, int b) { return inst[a].n > inst[b].n; });
+    const int pg = gmds::stored_components(P.p, P.latent);
+    P.desc.resize(n_inst);
+    P.prefix.assign(n_inst + 1, 0);
+    size_t floats = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        const gini_instance& I = inst[P.order[k]];
+        InstDesc& D = P.desc[k];
+        D = InstDesc{};
+        D.Delta = I.Delta;
+        D.Z = I.Z;
+        D.sigma_hist = I.sigma_hist;
+        D.n = I.n;
+        D.ldd = I.ldd;
+        D.ldz = I.ldz;
+        D.p = I.p;
+        double cc;
+        latent_consts(I.p, I.nu, I.latent, D, cc);
+        D.eta = I.eta > 0.f ? I.eta : (float)(1.0 / (2.0 * (double)I.n * cc));
+        const int64_t nt = layout(D, T);
+        D.tile_off = P.prefix[k];
+        P.prefix[k + 1] = P.prefix[k] + nt;
+        floats += partial_floats(D, T, pg);
+        floats = (floats + 63) & ~size_t(63);
+    }
+    P.tiles = P.prefix[n_inst];
+    if (P.tiles > (int64_t)0x7fffffff) return fail(c, GINI_EUNSUPPORTED, "too many tiles in one solve");
+    gini_status st = ensure_scratch(c, floats * sizeof(float));
+    if (st != GINI_OK) return st;
+    size_t off = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        assign_partials(P.desc[k], c->scratch + off, T, pg);
+        off += partial_floats(P.desc[k], T, pg);
+        off = (off + 63) & ~size_t(63);
+    }
+    return GINI_OK;
+}
+
+__global__ void k_reset_ctl(gmds::SolveCtl* ctl, uint32_t* cnt, uint32_t* ep, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        ctl->head = 0ull;
+        ctl->status = 0u;
+    }
+    if (i < n) {
+        cnt[i] = 0u;
+        ep[i] = 0u;
+    }
+}
+
+gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStream_t s) {
+    const int n_inst = (int)P.desc.size();
+    // one upload: descriptors, then the tile prefix
+    const size_t dbytes = (P.desc.size() * sizeof(InstDesc) + 15) & ~size_t(15);
+    std::vector<unsigned char> blob(dbytes + P.prefix.size() * sizeof(int64_t));
+    std::memcpy(blob.data(), P.desc.data(), P.desc.size() * sizeof(InstDesc));
+    std::memcpy(blob.data() + dbytes, P.prefix.data(), P.prefix.size() * sizeof(int64_t));
+    void* dd = nullptr;
+    Slot* sl = nullptr;
+    gini_status st = upload(c, blob.data(), blob.size(), s, &dd, &sl);
+    if (st != GINI_OK) return st;
+    const InstDesc* ddp = static_cast<const InstDesc*>(dd);
+    const int64_t* dprefix = reinterpret_cast<const int64_t*>(static_cast<unsigned char*>(dd) + dbytes);
+    if (mode == GINI_SOLVE_PLAIN) {
+        for (int k = 0; k < n_inst; ++k) {
+            const int64_t nt = P.prefix[k + 1] - P.prefix[k];
+            for (int it = 0; it < iters; ++it) {
+                {
+                    ProfScope ps(c, kProfTile, s);
+                    GINI_HIP(c, gmds::launch_stress_tiles(ddp + k, 1, nt, P.desc[k].tile_off, P.p, P.latent, P.T,
+                                                          true, s));
+                }
+                ProfScope ps(c, kProfReduce, s);
+                GINI_HIP(c, gmds::launch_stress_reduce(ddp + k, &P.desc[k], 1, P.p, P.latent, P.T, 1, it, s));
+            }
+        }
+    } else if (mode == GINI_SOLVE_BATCHED) {
+        for (int it = 0; it < iters; ++it) {
+            {
+                ProfScope ps(c, kProfTile, s);
+                GINI_HIP(c, gmds::launch_stress_tiles(ddp, n_inst, P.tiles, 0, P.p, P.latent, P.T, true, s));
+            }
+            ProfScope ps(c, kProfReduce, s);
+            GINI_HIP(c, gmds::launch_stress_reduce(ddp, P.desc.data(), n_inst, P.p, P.latent, P.T, 1, it, s));
+        }
+    } else {
+        st = ensure_ctl(c, n_inst);
+        if (st != GINI_OK) return st;
+        hipLaunchKernelGGL(k_reset_ctl, dim3((n_inst + 255) / 256), dim3(256), 0, s, c->ctl, c->counters,
+                           c->epochs, n_inst);
+        GINI_HIP(c, hipGetLastError());
+        int g = grid;
+        if (g <= 0) g = c->cus * gmds::persistent_max_blocks_per_cu(P.p, P.latent, P.T);
+        const int64_t cap = P.tiles * (int64_t)iters;
+        if (g > cap) g = (int)std::max<int64_t>(1, cap);
+        ProfScope ps(c, kProfPersistent, s);
+        GINI_HIP(c, gmds::launch_solve_persistent(ddp, n_inst, dprefix, P.tiles, iters, P.p, P.latent, P.T, g,
+                                                  c->ctl, c->counters, c->epochs, c->spin_limit, s));
+    }
+    st = slot_done(c, sl, s);
+    if (st != GINI_OK) return st;
+    GINI_HIP(c, hipStreamSynchronize(s));
+    if (mode == GINI_SOLVE_PERSISTENT) {
+        gmds::SolveCtl h{};
+        GINI_HIP(c, hipMemcpy(&h, c->ctl, sizeof h, hipMemcpyDeviceToHost));
+        if (h.status != gmds::kStatusOk)
+            return fail(c, GINI_EDEVICE, "persistent solve aborted: a dependency wait exceeded its time limit");
+    }
+    return GINI_OK;
+}
+
+int solve_mode(int flags) {
+    if (flags & GINI_SOLVE_PLAIN) return GINI_SOLVE_PLAIN;
+    if (flags & GINI_SOLVE_BATCHED) return GINI_SOLVE_BATCHED;
+    return GINI_SOLVE_PERSISTENT;
+}
+
+std::string tune_key(const gini_instance* inst, int32_t n_inst) {
+    std::vector<int64_t> ns(n_inst);
+    for (int k = 0; k < n_inst; ++k) ns[k] = inst[k].n;
+    std::sort(ns.begin(), ns.end());
+    std::string key = std::to_string(n_inst) + ":" + std::to_string(inst[0].p) + ":" + std::to_string(inst[0].latent);
+    uint64_t h = 1469598103934665603ull;
+    for (int64_t v : ns) {
+        h ^= (uint64_t)v;
+        h *= 1099511628211ull;
+    }
+    return key + ":" + std::to_string(h);
+}
+
+gini_status solve_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst, const gini_solve_opts* o,
+                       hipStream_t s);
+
+gini_status autotune_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst, int32_t probe_iters,
+                          gini_solve_opts* best, hipStream_t s) {
+    if (probe_iters < 1) probe_iters = 3;
+    struct ProfPause {
+        gini_ctx* c;
+        bool was;
+        explicit ProfPause(gini_ctx* c_) : c(c_), was(c_->prof) { c->prof = false; }
+        ~ProfPause() { c->prof = was; }
+    } pause(c);
+    // private copies of the configurations; histories are not recorded
+    std::vector<gini_instance> tmp(inst, inst + n_inst);
+    std::vector<float*> zcopy(n_inst, nullptr);
+    gini_status st = GINI_OK;
+    for (int k = 0; k < n_inst && st == GINI_OK; ++k) {
+        const size_t bytes = (size_t)((inst[k].n - 1) * inst[k].ldz + inst[k].p) * sizeof(float);
+        if (hipMalloc(reinterpret_cast<void**>(&zcopy[k]), bytes) != hipSuccess) {
+            st = fail(c, GINI_ENOMEM, "autotune: configuration copy failed");
+            break;
+        }
+        tmp[k].Z = zcopy[k];
+        tmp[k].sigma_hist = nullptr;
+    }
+    std::vector<gini_solve_opts> cand;
+    int64_t maxn = 0;
+    for (int k = 0; k < n_inst; ++k) maxn = std::max(maxn, inst[k].n);
+    for (int T : {64, 128, 256}) {
+        if (T > 64 && maxn <= T / 2) continue;
+        cand.push_back({probe_iters, GINI_SOLVE_BATCHED, T, 0});
+        int nb = gmds::persistent_max_blocks_per_cu(inst[0].p, inst[0].latent, T);
+        for (int g : {1, 2, 4, 8}) {
+            if (g > nb) break;
+            cand.push_back({probe_iters, GINI_SOLVE_PERSISTENT, T, g * c->cus});
+        }
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (st == GINI_OK) {
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+            st = fail(c, GINI_EDEVICE, "autotune: event creation failed");
+    }
+    float best_ms = 1e30f;
+    gini_solve_opts best_o{0, GINI_SOLVE_PERSISTENT, 0, 0};
+    for (size_t ci = 0; ci < cand.size() && st == GINI_OK; ++ci) {
+        for (int rep = 0; rep < 2 && st == GINI_OK; ++rep) {   // first run warms up
+            for (int k = 0; k < n_inst && st == GINI_OK; ++k) {
+                const size_t bytes = (size_t)((inst[k].n - 1) * inst[k].ldz + inst[k].p) * sizeof(float);
+                if (hipMemcpyAsync(zcopy[k], inst[k].Z, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                    st = fail(c, GINI_EDEVICE, "autotune: copy failed");
+            }
+            if (st != GINI_OK) break;
+            (void)hipEventRecord(e0, s);
+            st = solve_impl(c, tmp.data(), n_inst, &cand[ci], s);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (st == GINI_OK && rep == 1 && ms < best_ms) {
+                best_ms = ms;
+                best_o = cand[ci];
+            }
+        }
+    }
+    (void)hipStreamSynchronize(s);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    for (float* z : zcopy)
+        if (z) (void)hipFree(z);
+    if (st != GINI_OK) return st;
+    best_o.iters = 0;
+    c->tune[tune_key(inst, n_inst)] = TuneEntry{best_o};
+    *best = best_o;
+    return GINI_OK;
+}
+
+gini_status solve_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst, const gini_solve_opts* o,
+                       hipStream_t s) {
+    gini_solve_opts opts = *o;
+    if (opts.flags & GINI_SOLVE_AUTOTUNE) {
+        const std::string key = tune_key(inst, n_inst);
+        auto it = c->tune.find(key);
+        gini_solve_opts t{};
+        if (it == c->tune.end()) {
+            gini_status st = autotune_impl(c, inst, n_inst, 3, &t, s);
+            if (st != GINI_OK) return st;
+        } else {
+            t = it->second.opts;
+        }
+        opts.flags = (opts.flags & GINI_SOLVE_CHECK_FINITE) | t.flags;
+        opts.tile = t.tile;
+        opts.grid = t.grid;
+    }
+    int64_t maxn = 0;
+    for (int k = 0; k < n_inst; ++k) maxn = std::max(maxn, inst[k].n);
+    const int T = opts.tile > 0 ? opts.tile : pick_tile(maxn);
+    Plan P;
+    gini_status st = make_plan(c, inst, n_inst, T, P);
+    if (st != GINI_OK) return st;
+    if (opts.iters == 0) return GINI_OK;
+    st = run_plan(c, P, opts.iters, solve_mode(opts.flags), opts.grid, s);
+    if (st != GINI_OK) return st;
+    if (opts.flags & GINI_SOLVE_CHECK_FINITE) {
+        std::vector<float> h(opts.iters);
+        for (int k = 0; k < n_inst; ++k) {
+            if (!inst[k].sigma_hist) continue;
+            GINI_HIP(c, hipMemcpy(h.data(), inst[k].sigma_hist, h.size() * sizeof(float), hipMemcpyDeviceToHost));
+            for (float v : h)
+                if (!std::isfinite(v)) return fail(c, GINI_ENOTFINITE, "instance %d: stress is not finite", k);
+        }
+    }
+    return GINI_OK;
+}
+
+gini_status check_opts(gini_ctx* c, const gini_solve_opts* o) {
+    if (!o) return fail(c, GINI_EINVAL, "opts must be non-null");
+    if (o->iters < 0) return fail(c, GINI_EINVAL, "iters < 0");
+    const int modes = o->flags & (GINI_SOLVE_PERSISTENT | GINI_SOLVE_PLAIN | GINI_SOLVE_BATCHED);
+    if (modes & (modes - 1)) return fail(c, GINI_EINVAL, "choose one of PERSISTENT, PLAIN, BATCHED");
+    if (o->flags & ~(GINI_SOLVE_PERSISTENT | GINI_SOLVE_PLAIN | GINI_SOLVE_BATCHED | GINI_SOLVE_AUTOTUNE |
+                     GINI_SOLVE_CHECK_FINITE))
+        return fail(c, GINI_EINVAL, "unknown solve flag");
+    if (o->tile != 0 && o->tile != 64 && o->tile != 128 && o->tile != 256)
+        return fail(c, GINI_EINVAL, "tile must be 0, 64, 128 or 256");
+    if (o->grid < 0) return fail(c, GINI_EINVAL, "grid < 0");
+    return GINI_OK;
+}
+
+}  // namespace
+
+// ======================================================================= C ABI
+extern "C" {
+
+gini_status gini_create(gini_ctx** ctx, int device) {
+    if (!ctx) return GINI_EINVAL;
+    *ctx = nullptr;
+    if (device < 0) return GINI_EINVAL;
+    gini_ctx* c = new (std::nothrow) gini_ctx();
+    if (!c) return GINI_ENOMEM;
+    c->device = device;
+    if (const char* v = std::getenv("GINI_SPIN_LIMIT_TICKS")) {
+        const long long t = std::atoll(v);
+        if (t > 0) {
+            c->spin_limit = t;
+            c->spin_override = true;
+        }
+    }
+    *ctx = c;
+    return GINI_OK;
+}
+
+void gini_destroy(gini_ctx* c) {
+    if (!c) return;
+    if (c->ready) {
+        (void)hipSetDevice(c->device);
+        (void)hipDeviceSynchronize();
+        for (auto& kv : c->tables) (void)hipFree(kv.second);
+        if (c->scratch) (void)hipFree(c->scratch);
+        if (c->ctl) {
+            (void)hipFree(c->ctl);
+            (void)hipFree(c->counters);
+            (void)hipFree(c->epochs);
+        }
+        prof_clear(c);
+        for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+        for (auto& sl : c->ring) {
+            if (sl.host) (void)hipHostFree(sl.host);
+            if (sl.dev) (void)hipFree(sl.dev);
+            if (sl.done) (void)hipEventDestroy(sl.done);
+        }
+    }
+    delete c;
+}
+
+const char* gini_last_error(const gini_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+const char* gini_status_string(gini_status s) {
+    switch (s) {
+        case GINI_OK: return "GINI_OK";
+        case GINI_EINVAL: return "GINI_EINVAL";
+        case GINI_ENOMEM: return "GINI_ENOMEM";
+        case GINI_EDEVICE: return "GINI_EDEVICE";
+        case GINI_ENOTFINITE: return "GINI_ENOTFINITE";
+        case GINI_EUNSUPPORTED: return "GINI_EUNSUPPORTED";
+    }
+    return "unknown gini_status";
+}
+
+int gini_version(void) { return kVersion; }
+
+gini_status gini_weight_table(int32_t d, double nu, float* W) {
+    if (!W || d < 1 || d > 65536 || bad_nu(nu)) return GINI_EINVAL;
+    std::vector<double> w(2 * (size_t)d - 1);
+    weight_table(d, nu, w.data());
+    for (size_t i = 0; i < w.size(); ++i) W[i] = (float)w[i];
+    return GINI_OK;
+}
+
+gini_status gini_rank(gini_ctx* c, const float* V, int64_t rows, int32_t d, int64_t ldv, int32_t* twoR, int64_t ldr,
+                      gini_stream_t stream) {
+    if (!c) return GINI_EINVAL;
+    c->err.clear();
+    if (rows < 0) return fail(c, GINI_EINVAL, "rows < 0");
+    if (d < 1 || d > kMaxRankD) return fail(c, GINI_EINVAL, "d = %d outside 1..%lld", d, (long long)kMaxRankD);
+    if (ldv < d || ldr < d) return fail(c, GINI_EINVAL, "leading dimensions must be >= d");
+    if (rows > 0 && (!V || !twoR)) return fail(c, GINI_EINVAL, "V and twoR must be non-null");
+    if (rows > (int64_t)0x7fffffff) return fail(c, GINI_EUNSUPPORTED, "rows > 2^31 - 1");
+    if (rows == 0) return GINI_OK;
+    gini_status st = ensure_ready(c);
+    if (st != GINI_OK) return st;
+    GINI_HIP(c, gmds::launch_rank(V, rows, d, ldv, twoR, ldr, reinterpret_cast<hipStream_t>(stream)));
+    return GINI_OK;
+}
+
+gini_status gini_dissim(gini_ctx* c, const float* X, int64_t n, int32_t m, int64_t ldx, const double* nu, int32_t n_nu,
+                        float* Delta, int64_t ldd, int64_t stride_nu, gini_stream_t stream) {
+    if (!c) return GINI_EINVAL;
+    c->err.clear();
+    if (n < 1) return fail(c, GINI_EINVAL, "n = %lld < 1", (long long)n);
+    if (m < 1 || m > kMaxDissimM) return fail(c, GINI_EINVAL, "m = %d outside 1..%d", m, kMaxDissimM);
+    if (!X || !Delta || !nu) return fail(c, GINI_EINVAL, "X, nu and Delta must be non-null");
+    if (ldx < m) return fail(c, GINI_EINVAL, "ldx = %lld < m = %d", (long long)ldx, m);
+    if (ldd < n) return fail(c, GINI_EINVAL, "ldd = %lld < n = %lld", (long long)ldd, (long long)n);
+    if (n_nu < 1 || n_nu > gmds::kMaxNu) return fail(c, GINI_EINVAL, "n_nu = %d outside 1..%d", n_nu, gmds::kMaxNu);
+    for (int k = 0; k < n_nu; ++k)
+        if (bad_nu(nu[k])) return fail(c, GINI_EINVAL, "nu[%d] must be finite and > 1", k);
+    if (n_nu > 1 && stride_nu < n * ldd)
+        return fail(c, GINI_EINVAL, "stride_nu = %lld < n*ldd", (long long)stride_nu);
+    if (n > (int64_t)1 << 22) return fail(c, GINI_EUNSUPPORTED, "n > 2^22 is not supported");
+    gini_status st = ensure_ready(c);
+    if (st != GINI_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    float* w = nullptr;
+    st = get_tables(c, m, nu, n_nu, s, &w);
+    if (st != GINI_OK) return st;
+    gmds::DissimArgs a{};
+    a.X = X;
+    a.Delta = Delta;
+    a.wtab = w;
+    a.n = n;
+    a.ldx = ldx;
+    a.ldd = ldd;
+    a.stride_nu = n_nu > 1 ? stride_nu : 0;
+    a.m = m;
+    a.n_nu = n_nu;
+    a.half_m = 0.5f * (float)m;
+    ProfScope ps(c, kProfDissim, s);
+    GINI_HIP(c, gmds::launch_dissim(a, s));
+    return GINI_OK;
+}
+
+gini_status gini_stress_fwd(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, const float* Z, int32_t p,
+                            int64_t ldz, double nu, gini_latent latent, float* out_sigma, gini_stream_t stream) {
+    return stress_common(c, Delta, n, ldd, Z, p, ldz, nu, latent, nullptr, nullptr, p, out_sigma, false,
+                         reinterpret_cast<hipStream_t>(stream));
+}
+
+gini_status gini_stress_bwd(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, const float* Z, int32_t p,
+                            int64_t ldz, double nu, gini_latent latent, const float* grad_out, float* gradZ,
+                            int64_t ldg, float* out_sigma, gini_stream_t stream) {
+    return stress_common(c, Delta, n, ldd, Z, p, ldz, nu, latent, grad_out, gradZ, ldg, out_sigma, true,
+                         reinterpret_cast<hipStream_t>(stream));
+}
+
+gini_status gini_mds_solve(gini_ctx* c, const gini_instance* inst, int32_t n_inst, const gini_solve_opts* opts,
+                           gini_stream_t stream) {
+    if (!c) return GINI_EINVAL;
+    c->err.clear();
+    gini_status st = check_opts(c, opts);
+    if (st != GINI_OK) return st;
+    st = validate_instances(c, inst, n_inst);
+    if (st != GINI_OK) return st;
+    st = ensure_ready(c);
+    if (st != GINI_OK) return st;
+    return solve_impl(c, inst, n_inst, opts, reinterpret_cast<hipStream_t>(stream));
+}
+
+gini_status gini_profile_enable(gini_ctx* c, int enable) {
+    if (!c) return GINI_EINVAL;
+    c->err.clear();
+    if (c->ready) {
+        gini_status st = ensure_ready(c);
+        if (st != GINI_OK) return st;
+        for (auto& v : c->prof_ev)
+            for (auto& pr : v) (void)hipEventSynchronize(pr.second);
+    }
+    prof_clear(c);
+    c->prof = enable != 0;
+    return GINI_OK;
+}
+
+gini_status gini_profile_read(gini_ctx* c, gini_profile* out) {
+    if (!c || !out) return GINI_EINVAL;
+    c->err.clear();
+    std::memset(out, 0, sizeof *out);
+    if (!c->ready) return GINI_OK;
+    gini_status st = ensure_ready(c);
+    if (st != GINI_OK) return st;
+    int64_t* cnt[4] = {&out->tile_launches, &out->reduce_launches, &out->persistent_launches, &out->dissim_launches};
+    double* ms[4] = {&out->tile_ms, &out->reduce_ms, &out->persistent_ms, &out->dissim_ms};
+    for (int k = 0; k < 4; ++k) {
+        for (auto& pr : c->prof_ev[k]) {
+            GINI_HIP(c, hipEventSynchronize(pr.second));
+            float t = 0.f;
+            GINI_HIP(c, hipEventElapsedTime(&t, pr.first, pr.second));
+            *ms[k] += t;
+            *cnt[k] += 1;
+        }
+    }
+    prof_clear(c);
+    return GINI_OK;
+}
+
+gini_status gini_autotune(gini_ctx* c, const gini_instance* inst, int32_t n_inst, int32_t probe_iters,
+                          gini_solve_opts* best, gini_stream_t stream) {
+    if (!c) return GINI_EINVAL;
+    c->err.clear();
+    if (!best) return fail(c, GINI_EINVAL, "best must be non-null");
+    if (probe_iters < 1 || probe_iters > 1000) return fail(c, GINI_EINVAL, "probe_iters outside 1..1000");
+    gini_status st = validate_instances(c, inst, n_inst);
+    if (st != GINI_OK) return st;
+    st = ensure_ready(c);
+    if (st != GINI_OK) return st;
+    const int keep = best->flags & GINI_SOLVE_CHECK_FINITE;
+    st = autotune_impl(c, inst, n_inst, probe_iters, best, reinterpret_cast<hipStream_t>(stream));
+    if (st == GINI_OK) best->flags |= keep;
+    return st;
+}
+
+}  // extern "C"

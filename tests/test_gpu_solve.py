@@ -1,0 +1,127 @@
+"""GPU descent: the three launch modes agree bitwise, each step matches the
+oracle on the same iterate (teacher forcing), and the stress does not rise."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2605_25124_amd import synth
+from tests._util import rel
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def gm():
+    from paper_2605_25124_amd import ginimds
+    return ginimds
+
+
+def _instances(gm, sizes, p=2, latent=0, nus=(1.5, 2.0, 3.0), seed=0):
+    g = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k, (n, m) in enumerate(sizes):
+        X = synth.gaussian_mixture(g, n, m, 3, 0.05).astype(np.float32)
+        nu = nus[k % len(nus)]
+        D = gm.gini_dissim(torch.from_numpy(X).to(DEV), [nu])[0]
+        Z0 = torch.from_numpy((0.1 * g.standard_normal((n, p))).astype(np.float32)).to(DEV)
+        out.append((D, Z0, nu))
+    return out
+
+
+def _run(gm, probs, iters, flags, tile, latent=0, grid=0):
+    insts, Zs, hs = [], [], []
+    for D, Z0, nu in probs:
+        Z = Z0.clone()
+        h = torch.zeros(max(iters, 1), device=DEV)
+        insts.append(gm.Instance(D, Z, nu, latent, 0.0, h))
+        Zs.append(Z)
+        hs.append(h)
+    gm.gini_mds_solve(insts, iters, flags, tile, grid)
+    return [z.cpu() for z in Zs], [h.cpu() for h in hs]
+
+
+SIZES = [(130, 6), (900, 12), (70, 30), (1500, 5), (260, 64), (2, 3)]
+
+
+@pytest.mark.parametrize("tile", [64, 128, 256])
+def test_modes_bitwise_identical(gm, tile):
+    probs = _instances(gm, SIZES)
+    Zp, hp = _run(gm, probs, 7, gm.SOLVE_PLAIN, tile)
+    Zb, hb = _run(gm, probs, 7, gm.SOLVE_BATCHED, tile)
+    Zs, hs = _run(gm, probs, 7, gm.SOLVE_PERSISTENT, tile)
+    for k in range(len(SIZES)):
+        assert torch.equal(Zp[k], Zb[k]) and torch.equal(Zp[k], Zs[k]), k
+        assert torch.equal(hp[k], hb[k]) and torch.equal(hp[k], hs[k]), k
+
+
+def test_batched_equals_single_instance_runs(gm):
+    probs = _instances(gm, SIZES, seed=3)
+    Zs, hs = _run(gm, probs, 5, gm.SOLVE_PERSISTENT, 128)
+    for k, pr in enumerate(probs):
+        Z1, h1 = _run(gm, [pr], 5, gm.SOLVE_PERSISTENT, 128)
+        assert torch.equal(Z1[0], Zs[k]) and torch.equal(h1[0], hs[k]), k
+
+
+@pytest.mark.parametrize("latent,p", [(0, 2), (0, 3), (1, 2)])
+def test_teacher_forced_steps(gm, orc, latent, p):
+    probs = _instances(gm, [(300, 8)], p=p, latent=latent, nus=(2.5,), seed=5)
+    D, Z0, nu = probs[0]
+    Dn = D.cpu().numpy().astype(np.float64)
+    Z = Z0.clone()
+    eta = orc.step_size(300, p, nu, latent)
+    for t in range(4):
+        Zt = Z.cpu().numpy()
+        h = torch.zeros(1, device=DEV)
+        gm.gini_mds_solve([gm.Instance(D, Z, nu, latent, 0.0, h)], 1, gm.SOLVE_PERSISTENT)
+        s_ref, G_ref = orc.stress(Dn, Zt, nu, latent, orc.MATCH32)
+        assert abs(float(h[0]) - s_ref) <= 1e-4 * s_ref, t
+        step = (Zt.astype(np.float64) - Z.cpu().numpy().astype(np.float64)) / eta
+        assert rel(step, G_ref) <= 1e-4, (t, rel(step, G_ref))
+
+
+def test_small_workload_descends_like_oracle(gm, orc):
+    w = synth.workload_small()
+    X32 = w.X.astype(np.float32)
+    D = gm.gini_dissim(torch.from_numpy(X32).to(DEV), [2.0])[0]
+    Z = torch.from_numpy(w.Z0[0].astype(np.float32)).to(DEV)
+    h = torch.zeros(w.iters, device=DEV)
+    gm.gini_mds_solve([gm.Instance(D, Z, 2.0, 0, 0.0, h)], w.iters, gm.SOLVE_PERSISTENT)
+    hist = h.cpu().numpy().astype(np.float64)
+    assert np.all(np.diff(hist) <= 1e-5 * hist[0])
+    _, href = orc.solve(D.cpu().numpy().astype(np.float64), w.Z0[0], 2.0, w.iters, 0, orc.MATCH32)
+    assert abs(hist[-1] - href[-1]) <= 1e-3 * href[0]
+    assert abs(hist[0] - href[0]) <= 1e-4 * href[0]
+
+
+def test_autotune_and_solve(gm):
+    probs = _instances(gm, SIZES, seed=9)
+    insts = [gm.Instance(D, Z0.clone(), nu) for D, Z0, nu in probs]
+    best = gm.gini_autotune(insts, 2)
+    assert best["flags"] in (gm.SOLVE_PERSISTENT, gm.SOLVE_BATCHED)
+    assert best["tile"] in (64, 128, 256)
+    for I, (D, Z0, nu) in zip(insts, probs):
+        assert torch.equal(I.Z, Z0)                 # autotune works on copies
+    Za, ha = _run(gm, probs, 4, gm.SOLVE_AUTOTUNE, 0)
+    Zr, hr = _run(gm, probs, 4, best["flags"], best["tile"])
+    for k in range(len(probs)):
+        assert torch.equal(Za[k], Zr[k]) and torch.equal(ha[k], hr[k])
+
+
+def test_check_finite_flag(gm):
+    probs = _instances(gm, [(100, 4)], seed=2)
+    D, Z0, nu = probs[0]
+    Z = Z0.clone()
+    Z[5, 0] = float("nan")
+    h = torch.zeros(2, device=DEV)
+    with pytest.raises(gm.GiniError) as e:
+        gm.gini_mds_solve([gm.Instance(D, Z, nu, 0, 0.0, h)], 2, gm.SOLVE_PERSISTENT | gm.SOLVE_CHECK_FINITE)
+    assert e.value.status == 4
+
+
+def test_zero_iterations_is_noop(gm):
+    probs = _instances(gm, [(50, 4)], seed=4)
+    D, Z0, nu = probs[0]
+    Z = Z0.clone()
+    gm.gini_mds_solve([gm.Instance(D, Z, nu)], 0, gm.SOLVE_PERSISTENT)
+    assert torch.equal(Z, Z0)

@@ -1,0 +1,142 @@
+"""GPU parity of the fused stress forward/backward kernels against the FP64
+oracle, evaluated on the same FP32 inputs (Delta and Z)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2605_25124_amd import synth
+from tests._util import rel
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def gm():
+    from paper_2605_25124_amd import ginimds
+    return ginimds
+
+
+def _problem(gm, n, m, p, seed, nu=2.0, scale=0.5, ties=False):
+    g = np.random.Generator(np.random.PCG64(seed))
+    X = g.standard_normal((n, m)).astype(np.float32)
+    Z = (scale * g.standard_normal((n, p))).astype(np.float32)
+    if ties and n > 6:
+        Z[3] = Z[4]
+        Z[5, 0] = Z[5, 1]
+        Z[6, :] = 0.25
+    D = gm.gini_dissim(torch.from_numpy(X).to(DEV), [nu])[0]
+    return D, torch.from_numpy(Z).to(DEV)
+
+
+def _compare(gm, orc, D, Z, nu, latent, what):
+    G, sig = gm.gini_stress_bwd(D, Z, nu, latent)
+    s1 = gm.gini_stress_fwd(D, Z, nu, latent)
+    torch.cuda.synchronize()
+    Dn = D.cpu().numpy().astype(np.float64)
+    Zn = Z.cpu().numpy()
+    s_ref, G_ref = orc.stress(Dn, Zn, nu, latent, orc.MATCH32)
+    sg = float(sig[0].double() + sig[1].double())
+    sf = float(s1[0].double() + s1[1].double())
+    assert abs(sg - s_ref) <= 1e-4 * abs(s_ref), (what, sg, s_ref)
+    assert abs(sf - s_ref) <= 1e-4 * abs(s_ref), (what, sf, s_ref)
+    Gn = G.cpu().numpy()
+    assert rel(Gn, G_ref) <= 1e-4, (what, rel(Gn, G_ref))
+    return Gn, G_ref
+
+
+@pytest.mark.parametrize("n", [2, 3, 63, 64, 65, 200, 511, 513, 1000, 4097])
+@pytest.mark.parametrize("latent,p", [(0, 2), (0, 3), (1, 2)])
+def test_stress_parity_sizes(gm, orc, n, latent, p):
+    D, Z = _problem(gm, n, 6, p, 10 * n + p, nu=2.0)
+    _compare(gm, orc, D, Z, 2.0, latent, f"n={n} p={p} latent={latent}")
+
+
+@pytest.mark.parametrize("latent,p,nu", [(0, 2, 1.5), (0, 2, 3.7), (0, 3, 1.5), (0, 3, 3.0), (0, 4, 2.5),
+                                         (0, 5, 2.0), (0, 8, 1.7), (1, 1, 2.0), (1, 3, 2.0), (1, 6, 2.0)])
+def test_stress_parity_dims(gm, orc, latent, p, nu):
+    D, Z = _problem(gm, 300, 9, p, 77 + p, nu=nu)
+    _compare(gm, orc, D, Z, nu, latent, f"p={p} nu={nu} latent={latent}")
+
+
+@pytest.mark.parametrize("latent,p,nu", [(0, 2, 2.0), (0, 3, 1.5), (0, 4, 3.0), (1, 2, 2.0)])
+def test_stress_latent_ties(gm, orc, latent, p, nu):
+    D, Z = _problem(gm, 150, 5, p, 5, nu=nu, ties=True)
+    _compare(gm, orc, D, Z, nu, latent, "ties")
+
+
+def test_stress_unaligned_delta(gm, orc):
+    """ldd not a multiple of 4: the kernel takes its scalar-load path."""
+    g = np.random.Generator(np.random.PCG64(3))
+    n = 301
+    X = torch.from_numpy(g.standard_normal((n, 8)).astype(np.float32)).to(DEV)
+    buf = torch.empty((1, n, n), device=DEV)
+    D = gm.gini_dissim(X, [2.0], out=buf)[0]
+    assert D.stride(0) == n
+    Z = torch.from_numpy((0.5 * g.standard_normal((n, 2))).astype(np.float32)).to(DEV)
+    _compare(gm, orc, D, Z, 2.0, 0, "unaligned")
+
+
+def test_stress_deterministic_and_scaled(gm):
+    D, Z = _problem(gm, 700, 6, 3, 8)
+    G1, s1 = gm.gini_stress_bwd(D, Z, 2.0, 0)
+    G2, s2 = gm.gini_stress_bwd(D, Z, 2.0, 0)
+    assert torch.equal(G1, G2) and torch.equal(s1, s2)
+    go = torch.tensor([-2.5], device=DEV)
+    G3, _ = gm.gini_stress_bwd(D, Z, 2.0, 0, grad_out=go)
+    assert torch.allclose(G3, -2.5 * G1, rtol=1e-6, atol=0)
+
+
+def test_stress_zero_residual_fixed_point(gm):
+    """m == p and Z == X: the latent distances reproduce Delta exactly."""
+    g = np.random.Generator(np.random.PCG64(4))
+    X = torch.from_numpy(g.standard_normal((260, 3)).astype(np.float32)).to(DEV)
+    D = gm.gini_dissim(X, [2.0])[0]
+    G, s = gm.gini_stress_bwd(D, X.contiguous(), 2.0, 0)
+    sig = float(s[0] + s[1])
+    assert sig <= 1e-10 * float((D.double() ** 2).sum())
+    assert float(G.abs().max()) <= 1e-5 * 260 * float(D.abs().max())
+
+
+def test_autograd_function(gm, orc):
+    D, Z = _problem(gm, 400, 7, 2, 12, nu=2.0)
+    Zr = Z.clone().requires_grad_(True)
+    loss = gm.GiniStress.apply(D, Zr, 2.0, 0)
+    (3.0 * loss).backward()
+    G, s = gm.gini_stress_bwd(D, Z, 2.0, 0)
+    assert torch.allclose(Zr.grad, 3.0 * G, rtol=1e-6, atol=0)
+    assert abs(float(loss) - float(s[0] + s[1])) <= 1e-6 * abs(float(loss))
+    with torch.no_grad():
+        l2 = gm.GiniStress.apply(D, Z, 2.0, 0)
+    assert abs(float(l2) - float(loss)) <= 1e-6 * abs(float(loss))
+
+
+@pytest.mark.parametrize("latent,p", [(0, 2), (0, 3), (1, 2)])
+def test_gradient_against_central_differences(gm, orc, latent, p):
+    """The GPU gradient matches central differences of the FP64 oracle's stress
+    (ranks do not change inside the step) and, loosely, of the GPU's own."""
+    D, Z = _problem(gm, 60, 5, p, 21 + p)
+    G, _ = gm.gini_stress_bwd(D, Z, 2.0, latent)
+    Gn = G.cpu().numpy()
+    Dn = D.cpu().numpy().astype(np.float64)
+    Zn = Z.cpu().numpy().astype(np.float64)
+    h = 1e-6
+    for i in (0, 17, 59):
+        for c in range(p):
+            Zp, Zm = Zn.copy(), Zn.copy()
+            Zp[i, c] += h
+            Zm[i, c] -= h
+            fd = (orc.stress(Dn, Zp, 2.0, latent, orc.EXACT, grad=False)[0]
+                  - orc.stress(Dn, Zm, 2.0, latent, orc.EXACT, grad=False)[0]) / (2 * h)
+            assert abs(Gn[i, c] - fd) <= 1e-4 * np.abs(Gn).max(), (i, c, Gn[i, c], fd)
+    # the GPU's own FP32 stress, step large against rounding, small against the kinks
+    h32 = 1e-3
+    for i in (3, 40):
+        for c in range(p):
+            Zp, Zm = Z.clone(), Z.clone()
+            Zp[i, c] += h32
+            Zm[i, c] -= h32
+            sp = gm.gini_stress_fwd(D, Zp, 2.0, latent)
+            sm = gm.gini_stress_fwd(D, Zm, 2.0, latent)
+            fd = (float(sp[0].double() + sp[1].double()) - float(sm[0].double() + sm[1].double())) / (2 * h32)
+            assert abs(Gn[i, c] - fd) <= 2e-2 * np.abs(Gn).max(), (i, c, Gn[i, c], fd)
