@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--mode", choices=["auto", "persistent", "batched"], default="auto")
+    ap.add_argument("--tile", type=int, default=256)
     return ap.parse_args()
 
 
@@ -95,7 +96,7 @@ def main():
         best = gm.gini_autotune([inst(Z0.clone())], 3)
     else:
         best = {"flags": gm.SOLVE_PERSISTENT if args.mode == "persistent" else gm.SOLVE_BATCHED,
-                "tile": 256, "grid": 0}
+                "tile": args.tile, "grid": 0}
     mode_name = "persistent" if best["flags"] == gm.SOLVE_PERSISTENT else "batched"
     log(f"mode {mode_name} tile {best['tile']} grid {best['grid']}")
 
@@ -122,7 +123,7 @@ def main():
     # dominant kernel and its algorithmic traffic per launch
     alg_bytes = 4.0 * pairs + 4.0 * n * p + 4.0 * n * p
     if prof["tile_launches"] > 0:
-        kname = "k_stress_tiles"
+        kname = "k_stress_units"
         launches = prof["tile_launches"]
         avg_ms = prof["tile_ms"] / launches
     else:

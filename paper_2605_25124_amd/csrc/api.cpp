@@ -60,9 +60,11 @@ struct gini_ctx {
     // scratch for tile partials (grown on demand)
     float* scratch = nullptr;
     size_t scratch_bytes = 0;
+    // completion counters of the fused reductions: zero between launches
+    uint32_t* cnt = nullptr;
+    size_t cnt_cap = 0;      // words
     // persistent-solve control
     gmds::SolveCtl* ctl = nullptr;
-    uint32_t* counters = nullptr;
     uint32_t* epochs = nullptr;
     size_t ctl_cap = 0;      // instances
     Slot ring[kRing];
@@ -217,16 +219,32 @@ gini_status ensure_ctl(gini_ctx* c, size_t n_inst) {
     if (c->ctl) {
         GINI_HIP(c, hipDeviceSynchronize());
         (void)hipFree(c->ctl);
-        (void)hipFree(c->counters);
         (void)hipFree(c->epochs);
         c->ctl = nullptr;
     }
     size_t cap = std::max<size_t>(n_inst, 64);
     if (hipMalloc(reinterpret_cast<void**>(&c->ctl), sizeof(gmds::SolveCtl)) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&c->counters), cap * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&c->epochs), cap * sizeof(uint32_t)) != hipSuccess)
         return fail(c, GINI_ENOMEM, "solve control allocation failed");
     c->ctl_cap = cap;
+    return GINI_OK;
+}
+
+// Counter words for the fused reductions.  They are zero when no launch is in
+// flight (every launch leaves them as it found them); fresh memory is zeroed
+// on the stream before first use.
+gini_status ensure_counters(gini_ctx* c, size_t words, hipStream_t s) {
+    if (words <= c->cnt_cap && c->cnt) return GINI_OK;
+    if (c->cnt) {
+        GINI_HIP(c, hipDeviceSynchronize());
+        (void)hipFree(c->cnt);
+        c->cnt = nullptr;
+    }
+    size_t cap = std::max<size_t>(words, 4096);
+    if (hipMalloc(reinterpret_cast<void**>(&c->cnt), cap * sizeof(uint32_t)) != hipSuccess)
+        return fail(c, GINI_ENOMEM, "counter allocation failed");
+    c->cnt_cap = cap;
+    GINI_HIP(c, gmds::launch_fill_u32(c->cnt, (int64_t)cap, 0u, s));
     return GINI_OK;
 }
 
@@ -306,23 +324,27 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-// Fill the layout fields of one stress descriptor for tile size T; returns tiles.
+// Fill the layout fields of one stress descriptor for tile size T; returns
+// its number of work units.
 int64_t layout(InstDesc& D, int T) {
     D.nb = cdiv(D.n, T);
     D.vec = (aligned16(D.Delta) && (D.ldd % 4) == 0) ? 1 : 0;
-    return gmds::tri_count(D.nb);
+    return gmds::tri_count(D.nb) * gmds::units_per_tile(T);
 }
 
 size_t partial_floats(const InstDesc& D, int T, int pg) {
     const int64_t nt = gmds::tri_count(D.nb);
-    return (size_t)nt * T * pg * 2 + (size_t)nt * 2;
+    const int64_t u = gmds::units_per_tile(T);
+    return (size_t)nt * T * pg + (size_t)nt * u * T * pg + (size_t)nt * u * gmds::kStressWaves * 2 + 32;
 }
 
 void assign_partials(InstDesc& D, float* base, int T, int pg) {
     const int64_t nt = gmds::tri_count(D.nb);
+    const int64_t u = gmds::units_per_tile(T);
     D.rowpart = base;
     D.colpart = base + (size_t)nt * T * pg;
-    D.sigpart = base + (size_t)nt * T * pg * 2;
+    D.sigpart = D.colpart + (size_t)nt * u * T * pg;
+    D.sigslice = D.sigpart + (size_t)nt * u * gmds::kStressWaves * 2;
 }
 
 gini_status stress_common(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, const float* Z, int32_t p,
@@ -365,6 +387,9 @@ gini_status stress_common(gini_ctx* c, const float* Delta, int64_t n, int64_t ld
     st = ensure_scratch(c, partial_floats(D, T, pg) * sizeof(float));
     if (st != GINI_OK) return st;
     assign_partials(D, c->scratch, T, pg);
+    st = ensure_counters(c, 1, s);
+    if (st != GINI_OK) return st;
+    D.instcnt = c->cnt;
     D.tile_off = 0;
     void* dd = nullptr;
     Slot* sl = nullptr;
@@ -373,11 +398,12 @@ gini_status stress_common(gini_ctx* c, const float* Delta, int64_t n, int64_t ld
     const InstDesc* ddp = static_cast<const InstDesc*>(dd);
     {
         ProfScope ps(c, kProfTile, s);
-        GINI_HIP(c, gmds::launch_stress_tiles(ddp, 1, nt, 0, p, latent, T, grad, s));
+        GINI_HIP(c, gmds::launch_stress_units(ddp, 1, nt, 0, p, latent, T, grad, s));
     }
     {
         ProfScope ps(c, kProfReduce, s);
-        GINI_HIP(c, gmds::launch_stress_reduce(ddp, &D, 1, p, latent, T, grad ? 0 : 2, 0, s));
+        GINI_HIP(c, gmds::launch_stress_reduce(ddp, &D, 1, p, latent, T, grad ? gmds::kModeGrad : gmds::kModeSigma,
+                                               0, s));
     }
     return slot_done(c, sl, s);
 }
@@ -417,7 +443,7 @@ gini_status validate_instances(gini_ctx* c, const gini_instance* inst, int32_t n
     return GINI_OK;
 }
 
-gini_status make_plan(gini_ctx* c, const gini_instance* inst, int32_t n_inst, int T, Plan& P) {
+gini_status make_plan(gini_ctx* c, const gini_instance* inst, int32_t n_inst, int T, Plan& P, hipStream_t s) {
     P.p = inst[0].p;
     P.latent = inst[0].latent;
     P.T = T;
@@ -453,25 +479,25 @@ gini_status make_plan(gini_ctx* c, const gini_instance* inst, int32_t n_inst, in
     if (P.tiles > (int64_t)0x7fffffff) return fail(c, GINI_EUNSUPPORTED, "too many tiles in one solve");
     gini_status st = ensure_scratch(c, floats * sizeof(float));
     if (st != GINI_OK) return st;
+    st = ensure_counters(c, (size_t)n_inst, s);
+    if (st != GINI_OK) return st;
     size_t off = 0;
     for (int k = 0; k < n_inst; ++k) {
         assign_partials(P.desc[k], c->scratch + off, T, pg);
         off += partial_floats(P.desc[k], T, pg);
         off = (off + 63) & ~size_t(63);
+        P.desc[k].instcnt = c->cnt + k;
     }
     return GINI_OK;
 }
 
-__global__ void k_reset_ctl(gmds::SolveCtl* ctl, uint32_t* cnt, uint32_t* ep, int n) {
+__global__ void k_reset_ctl(gmds::SolveCtl* ctl, uint32_t* ep, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) {
         ctl->head = 0ull;
         ctl->status = 0u;
     }
-    if (i < n) {
-        cnt[i] = 0u;
-        ep[i] = 0u;
-    }
+    if (i < n) ep[i] = 0u;
 }
 
 gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStream_t s) {
@@ -489,31 +515,32 @@ gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStr
     const int64_t* dprefix = reinterpret_cast<const int64_t*>(static_cast<unsigned char*>(dd) + dbytes);
     if (mode == GINI_SOLVE_PLAIN) {
         for (int k = 0; k < n_inst; ++k) {
-            const int64_t nt = P.prefix[k + 1] - P.prefix[k];
+            const int64_t nu = P.prefix[k + 1] - P.prefix[k];
             for (int it = 0; it < iters; ++it) {
                 {
                     ProfScope ps(c, kProfTile, s);
-                    GINI_HIP(c, gmds::launch_stress_tiles(ddp + k, 1, nt, P.desc[k].tile_off, P.p, P.latent, P.T,
+                    GINI_HIP(c, gmds::launch_stress_units(ddp + k, 1, nu, P.desc[k].tile_off, P.p, P.latent, P.T,
                                                           true, s));
                 }
                 ProfScope ps(c, kProfReduce, s);
-                GINI_HIP(c, gmds::launch_stress_reduce(ddp + k, &P.desc[k], 1, P.p, P.latent, P.T, 1, it, s));
+                GINI_HIP(c, gmds::launch_stress_reduce(ddp + k, &P.desc[k], 1, P.p, P.latent, P.T,
+                                                       gmds::kModeDescent, it, s));
             }
         }
     } else if (mode == GINI_SOLVE_BATCHED) {
         for (int it = 0; it < iters; ++it) {
             {
                 ProfScope ps(c, kProfTile, s);
-                GINI_HIP(c, gmds::launch_stress_tiles(ddp, n_inst, P.tiles, 0, P.p, P.latent, P.T, true, s));
+                GINI_HIP(c, gmds::launch_stress_units(ddp, n_inst, P.tiles, 0, P.p, P.latent, P.T, true, s));
             }
             ProfScope ps(c, kProfReduce, s);
-            GINI_HIP(c, gmds::launch_stress_reduce(ddp, P.desc.data(), n_inst, P.p, P.latent, P.T, 1, it, s));
+            GINI_HIP(c, gmds::launch_stress_reduce(ddp, P.desc.data(), n_inst, P.p, P.latent, P.T,
+                                                   gmds::kModeDescent, it, s));
         }
     } else {
         st = ensure_ctl(c, n_inst);
         if (st != GINI_OK) return st;
-        hipLaunchKernelGGL(k_reset_ctl, dim3((n_inst + 255) / 256), dim3(256), 0, s, c->ctl, c->counters,
-                           c->epochs, n_inst);
+        hipLaunchKernelGGL(k_reset_ctl, dim3((n_inst + 255) / 256), dim3(256), 0, s, c->ctl, c->epochs, n_inst);
         GINI_HIP(c, hipGetLastError());
         int g = grid;
         if (g <= 0) g = c->cus * gmds::persistent_max_blocks_per_cu(P.p, P.latent, P.T);
@@ -521,7 +548,7 @@ gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStr
         if (g > cap) g = (int)std::max<int64_t>(1, cap);
         ProfScope ps(c, kProfPersistent, s);
         GINI_HIP(c, gmds::launch_solve_persistent(ddp, n_inst, dprefix, P.tiles, iters, P.p, P.latent, P.T, g,
-                                                  c->ctl, c->counters, c->epochs, c->spin_limit, s));
+                                                  c->ctl, c->epochs, c->spin_limit, s));
     }
     st = slot_done(c, sl, s);
     if (st != GINI_OK) return st;
@@ -529,8 +556,12 @@ gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStr
     if (mode == GINI_SOLVE_PERSISTENT) {
         gmds::SolveCtl h{};
         GINI_HIP(c, hipMemcpy(&h, c->ctl, sizeof h, hipMemcpyDeviceToHost));
-        if (h.status != gmds::kStatusOk)
+        if (h.status != gmds::kStatusOk) {
+            // the aborted launch left completion counters mid-count: clear them
+            GINI_HIP(c, gmds::launch_fill_u32(c->cnt, (int64_t)c->cnt_cap, 0u, s));
+            GINI_HIP(c, hipStreamSynchronize(s));
             return fail(c, GINI_EDEVICE, "persistent solve aborted: a dependency wait exceeded its time limit");
+        }
     }
     return GINI_OK;
 }
@@ -651,7 +682,7 @@ gini_status solve_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst, c
     for (int k = 0; k < n_inst; ++k) maxn = std::max(maxn, inst[k].n);
     const int T = opts.tile > 0 ? opts.tile : pick_tile(maxn);
     Plan P;
-    gini_status st = make_plan(c, inst, n_inst, T, P);
+    gini_status st = make_plan(c, inst, n_inst, T, P, s);
     if (st != GINI_OK) return st;
     if (opts.iters == 0) return GINI_OK;
     st = run_plan(c, P, opts.iters, solve_mode(opts.flags), opts.grid, s);
@@ -714,9 +745,9 @@ void gini_destroy(gini_ctx* c) {
         if (c->scratch) (void)hipFree(c->scratch);
         if (c->ctl) {
             (void)hipFree(c->ctl);
-            (void)hipFree(c->counters);
             (void)hipFree(c->epochs);
         }
+        if (c->cnt) (void)hipFree(c->cnt);
         prof_clear(c);
         for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
         for (auto& sl : c->ring) {

@@ -1,44 +1,79 @@
 // k_stress.hip -- fused raw-stress forward + backward over the upper triangle of
-// Delta, its deterministic reduction, and the persistent multi-instance solver.
+// Delta, the deterministic reduction of its partial sums, and the persistent
+// multi-instance solver.
 //
 // Work decomposition.  The strict upper triangle {i < j} of an n x n problem is
-// cut into T x T tiles (I, J), I <= J, enumerated row by row (tri_index).  One
-// 256-thread workgroup streams one tile of Delta exactly once: every thread owns
-// CPT consecutive-in-groups-of-4 columns of the tile (16-byte loads, LPR lanes
-// cover one 4*LPR*... row segment contiguously) and walks down the rows.  For
-// each pair it re-ranks the p latent coordinates of u = Z_i - Z_j, forms the
-// latent distance delta, the residual r = delta - Delta_ij, r^2, and the
-// gradient contribution g = 2 r * d delta / d Z_i (added to row i and
-// subtracted from column j).  Per tile it writes row partials, column partials
-// and the stress (hi, lo) to scratch; a second pass sums them in a fixed order
-// (Neumaier), so every result is deterministic and independent of scheduling.
+// cut into T x T tiles (I, J), I <= J, enumerated row by row (tri_index), and
+// every tile into T/UR work units of UR consecutive rows.  One 256-thread
+// workgroup streams one unit of Delta exactly once.  Sixteen lanes (one DPP
+// row) cover a tile row: lane c4 owns the columns 4*(c4 + 16q) .. +3, q < T/64,
+// read as 16-byte global loads, so each load instruction fetches 256 contiguous
+// bytes of the row; the workgroup walks 16 rows per step and the loads of the
+// next step are in flight while the current one is computed.  For each pair it
+// re-ranks the p latent coordinates of u = Z_i - Z_j, forms the latent distance
+// delta, the residual r = delta - Delta_ij, r^2 and the gradient term
+// r * d delta / d Z_i (added to row i, subtracted from column j; the common
+// factor 2 -- 2 * 2^(1-nu) for p = 2 Gini -- is applied once per point).
+//
+// Reduction.  A unit writes one partial per row (complete for that tile), one
+// partial per column and its stress.  A second launch sums, for every point, the
+// row partials of its tile row and the column partials of its tile column in a
+// fixed order (sixteen interleaved Neumaier sums combined in index order), and
+// either writes the gradient or takes the descent step.  No floating-point
+// atomics anywhere: results are bitwise reproducible and independent of
+// scheduling and of how many instances share a launch.
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace gmds {
 
 constexpr int kWG = 256;
+constexpr int kLPR = 16;                 // lanes per tile row = one DPP row
+constexpr int kRPS = kWG / kLPR;         // rows per step
+constexpr int kUR = 64;                  // rows per work unit
+constexpr int kUnitSteps = kUR / kRPS;   // steps per unit
+constexpr int kSplit = 16;               // interleaved partial sums per point in the reduction
+constexpr int kBatch = 4;                // loads in flight per partial sum
+constexpr int kWaves = kStressWaves;     // waves per workgroup (one stress partial each)
+static_assert(kWaves * 64 == kWG, "one stress partial per wave");
 
-template <int T> struct TileShape;
-template <> struct TileShape<64> { static constexpr int CPT = 4; };
-template <> struct TileShape<128> { static constexpr int CPT = 8; };
-template <> struct TileShape<256> { static constexpr int CPT = 8; };
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const f4v gf4;
+typedef __attribute__((address_space(1))) const float gfl;
+typedef __attribute__((address_space(1))) float gflw;
+
+__device__ __forceinline__ gfl* gp(const float* p) { return (gfl*)p; }
+__device__ __forceinline__ gflw* gpw(float* p) { return (gflw*)p; }
+
+template <int T> struct TileShape {
+    static constexpr int CPT = T / kLPR;      // columns per thread
+    static constexpr int NQ = CPT / 4;        // 16-byte loads per thread and row
+    static constexpr int UNITS = T / kUR;     // work units per tile
+};
 
 template <int P, int LAT>
 struct PG_ { static constexpr int value = (P == 2 && LAT == 0) ? 1 : P; };
 
-// LDS floats needed by stress_tile.
-template <int P, int LAT, int T>
-constexpr int tile_lds_floats() {
-    return (kWG / (T / TileShape<T>::CPT)) * T * PG_<P, LAT>::value;
+// Sum over the 16 lanes of a DPP row by rotations; every lane ends with a
+// total and lane 0 of the row is the one used (fixed order).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float row16_sum(float x) {
+    x += dpp_f<0x128>(x);   // row_ror:8
+    x += dpp_f<0x124>(x);   // row_ror:4
+    x += dpp_f<0x122>(x);   // row_ror:2
+    x += dpp_f<0x121>(x);   // row_ror:1
+    return x;
 }
 
-// Latent distance and residual for one pair.  `valid` masks pairs outside the
-// strict upper triangle or past n: they contribute exactly zero.
-//   u_c = fl32(Z_i,c - Z_j,c); Gini: doubled midranks t_c of u over its p
-//   coordinates, a_c = (p/2) W_p[t_c], delta = sum_c u_c a_c; Euclid:
-//   delta = |u|, a = u / |u| (0 when u = 0).  g_c = 2 r a_c.
-template <int P, int LAT, bool GRAD>
+// Stress term of one pair and its gradient term g (without the common factor).
+// MASK: `valid` zeroes pairs outside the strict upper triangle or past n.
+// u_c = fl32(Z_i,c - Z_j,c).  Gini: doubled midranks t_c of u over its p
+// coordinates, a_c = (p/2) W_p[t_c], delta = sum_c u_c a_c, g = r a.
+// Euclid: delta = |u|, g = r u / |u| (0 when u = 0).
+template <int P, int LAT, bool GRAD, bool MASK>
 __device__ __forceinline__ float pair_term(const float (&zi)[P], const float (&zj)[P], float d, bool valid,
                                            int p, const InstDesc& D, float (&g)[PG_<P, LAT>::value]) {
     constexpr int PG = PG_<P, LAT>::value;
@@ -46,15 +81,13 @@ __device__ __forceinline__ float pair_term(const float (&zi)[P], const float (&z
 #pragma unroll
     for (int c = 0; c < P; ++c) u[c] = zi[c] - zj[c];
     if constexpr (P == 2 && LAT == 0) {
-        // p = 2: t = (2,4) if u1 < u2, (4,2) if u1 > u2, (3,3) on a tie, so
-        // delta = 2^(1-nu) |u2 - u1| and a = 2^(1-nu) sgn(u2 - u1) (-1, +1).
+        // t = (2,4) if u1 < u2, (4,2) if u1 > u2, (3,3) on a tie, hence
+        // delta = 2^(1-nu) |u2 - u1| and a = 2^(1-nu) sgn(u2 - u1) (-1, +1);
+        // g keeps r sgn(u2 - u1), the second component.
         const float w = u[1] - u[0];
-        const float delta = D.c2 * fabsf(w);
-        const float r = valid ? (delta - d) : 0.f;
-        if constexpr (GRAD) {
-            const float s = (w > 0.f) ? 1.f : ((w < 0.f) ? -1.f : 0.f);
-            g[0] = 2.f * D.c2 * r * s;
-        }
+        float r = fmaf(D.c2, fabsf(w), -d);
+        if constexpr (MASK) r = valid ? r : 0.f;
+        if constexpr (GRAD) g[0] = (w > 0.f) ? r : ((w < 0.f) ? -r : 0.f);
         return r * r;
     } else if constexpr (LAT == 0) {
         float a[P];
@@ -72,10 +105,11 @@ __device__ __forceinline__ float pair_term(const float (&zi)[P], const float (&z
             a[c] = w;
             delta = fmaf(u[c], w, delta);
         }
-        const float r = valid ? (delta - d) : 0.f;
+        float r = delta - d;
+        if constexpr (MASK) r = valid ? r : 0.f;
         if constexpr (GRAD) {
 #pragma unroll
-            for (int c = 0; c < PG; ++c) g[c] = 2.f * r * a[c];
+            for (int c = 0; c < PG; ++c) g[c] = r * a[c];
         }
         return r * r;
     } else {
@@ -83,10 +117,10 @@ __device__ __forceinline__ float pair_term(const float (&zi)[P], const float (&z
 #pragma unroll
         for (int c = 0; c < P; ++c) ss = fmaf(u[c], u[c], ss);
         const float rs = (ss > 0.f) ? rsqrtf(ss) : 0.f;
-        const float delta = ss * rs;
-        const float r = valid ? (delta - d) : 0.f;
+        float r = fmaf(ss, rs, -d);
+        if constexpr (MASK) r = valid ? r : 0.f;
         if constexpr (GRAD) {
-            const float f = 2.f * r * rs;
+            const float f = r * rs;
 #pragma unroll
             for (int c = 0; c < PG; ++c) g[c] = f * u[c];
         }
@@ -94,213 +128,371 @@ __device__ __forceinline__ float pair_term(const float (&zi)[P], const float (&z
     }
 }
 
-// Stream one tile (local index lt of instance D) of Delta.
-template <int P, int LAT, int T, bool GRAD>
-__device__ void stress_tile(const InstDesc& D, int64_t lt, float* lds) {
-    constexpr int CPT = TileShape<T>::CPT;
-    constexpr int LPR = T / CPT;          // lanes per tile row
-    constexpr int RPS = kWG / LPR;        // rows per step
-    constexpr int STEPS = T / RPS;
-    constexpr int NQ = CPT / 4;
-    constexpr int PG = PG_<P, LAT>::value;
-    static_assert(LPR <= 64 && (64 % LPR) == 0, "a tile row must sit inside one wave");
-
+// Fixed-shape workgroup sum of compensated pairs; every thread gets the total.
+__device__ Comp wg_sum(Comp v, float* lds) {
     const int tid = threadIdx.x;
-    const int c4 = tid % LPR;
-    const int rr = tid / LPR;
-    int64_t I, J;
-    tri_decode(lt, D.nb, I, J);
+    __syncthreads();
+    lds[tid] = v.hi;
+    lds[kWG + tid] = v.lo;
+    __syncthreads();
+#pragma unroll
+    for (int st = kWG / 2; st > 0; st >>= 1) {
+        if (tid < st) {
+            Comp a;
+            a.hi = lds[tid];
+            a.lo = lds[kWG + tid];
+            Comp b;
+            b.hi = lds[tid + st];
+            b.lo = lds[kWG + tid + st];
+            a.add(b);
+            lds[tid] = a.hi;
+            lds[kWG + tid] = a.lo;
+        }
+        __syncthreads();
+    }
+    Comp r;
+    r.hi = lds[0];
+    r.lo = lds[kWG];
+    __syncthreads();
+    return r;
+}
+
+// LDS floats used by one unit: the latent rows of the unit, the column
+// reduction (16 row groups x T) and the stress tree.
+template <int P, int T>
+constexpr int unit_lds_floats() {
+    return kUR * P + (kRPS * T > 2 * kWG ? kRPS * T : 2 * kWG);
+}
+
+// Stream unit `sub` (rows I*T + sub*UR ..) of tile lt = (I, J) of instance D:
+// row partials rowpart[lt][row], column partials colpart[lt][sub][col] (GRAD)
+// and its stress, one (hi, lo) per wave: sigpart[(lt*UNITS + sub)*kWaves + w].
+template <int P, int LAT, int T, bool GRAD, bool MASK>
+__device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int64_t J, float* lds) {
+    constexpr int CPT = TileShape<T>::CPT;
+    constexpr int NQ = TileShape<T>::NQ;
+    constexpr int UNITS = TileShape<T>::UNITS;
+    constexpr int PG = PG_<P, LAT>::value;
+    const int tid = threadIdx.x;
+    const int c4 = tid % kLPR;
+    const int rr = tid / kLPR;
     const int64_t n = D.n;
-    const int64_t i0 = I * T;
+    const int64_t i0 = I * T + sub * kUR;
     const int64_t j0 = J * T;
     const int p = (P == kMaxP) ? D.p : P;
+    gfl* Zg = gp(D.Z);
+    float* zrow = lds;                                  // [kUR][P]
+    float* red = lds + kUR * P;
 
+    // latent rows of this unit into LDS; latent columns into registers
+    for (int x = tid; x < kUR * P; x += kWG) {
+        const int r = x / P, c = x % P;
+        const int64_t i = i0 + r;
+        zrow[x] = (c < p && (!MASK || i < n)) ? Zg[i * D.ldz + c] : 0.f;
+    }
     float zj[CPT][P];
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int64_t j = j0 + 4 * (c4 + q * LPR) + e;
+            const int64_t j = j0 + 4 * (c4 + q * kLPR) + e;
 #pragma unroll
-            for (int c = 0; c < P; ++c)
-                zj[q * 4 + e][c] = (j < n && c < p) ? D.Z[j * D.ldz + c] : 0.f;
+            for (int c = 0; c < P; ++c) {
+                if constexpr (MASK) zj[q * 4 + e][c] = (j < n && c < p) ? Zg[j * D.ldz + c] : 0.f;
+                else zj[q * 4 + e][c] = (c < p) ? Zg[j * D.ldz + c] : 0.f;
+            }
         }
-
     float colacc[CPT][PG];
 #pragma unroll
     for (int x = 0; x < CPT; ++x)
 #pragma unroll
         for (int c = 0; c < PG; ++c) colacc[x][c] = 0.f;
     Comp sig;
+    __syncthreads();
 
-#pragma unroll 2
-    for (int s = 0; s < STEPS; ++s) {
-        const int il = s * RPS + rr;
-        const int64_t i = i0 + il;
+    // Delta loads for one step of the unit (unmasked: 16-byte global loads)
+    auto load_step = [&](int s, f4v (&buf)[NQ]) {
+        const int64_t i = i0 + s * kRPS + rr;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int64_t jb = j0 + 4 * (c4 + q * kLPR);
+            if constexpr (!MASK) {
+                buf[q] = *(gf4*)(D.Delta + i * D.ldd + jb);
+            } else {
+                f4v v = {0.f, 0.f, 0.f, 0.f};
+                if (i < n && jb + 3 > i && jb < n) {
+                    const float* Dr = D.Delta + i * D.ldd;
+                    if (D.vec && jb + 3 < n) {
+                        v = *(gf4*)(Dr + jb);
+                    } else {
+                        if (jb + 0 < n && jb + 0 > i) v.x = gp(Dr)[jb + 0];
+                        if (jb + 1 < n && jb + 1 > i) v.y = gp(Dr)[jb + 1];
+                        if (jb + 2 < n && jb + 2 > i) v.z = gp(Dr)[jb + 2];
+                        if (jb + 3 < n && jb + 3 > i) v.w = gp(Dr)[jb + 3];
+                    }
+                }
+                buf[q] = v;
+            }
+        }
+    };
+    auto compute_step = [&](int s, const f4v (&buf)[NQ]) {
+        const int il = sub * kUR + s * kRPS + rr;          // row within the tile
+        const int64_t i = I * T + il;
+        float zi[P];
+#pragma unroll
+        for (int c = 0; c < P; ++c) zi[c] = zrow[(s * kRPS + rr) * P + c];
         float rowacc[PG];
 #pragma unroll
         for (int c = 0; c < PG; ++c) rowacc[c] = 0.f;
         float sst = 0.f;
-        if (i < n) {
-            float zi[P];
-#pragma unroll
-            for (int c = 0; c < P; ++c) zi[c] = (c < p) ? D.Z[i * D.ldz + c] : 0.f;
-            const float* Dr = D.Delta + i * D.ldd;
-            float dv[CPT];
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const int64_t jb = j0 + 4 * (c4 + q * LPR);
-                dv[q * 4 + 0] = dv[q * 4 + 1] = dv[q * 4 + 2] = dv[q * 4 + 3] = 0.f;
-                if (jb + 3 > i && jb < n) {
-                    if (D.vec && jb + 3 < n) {
-                        const float4 v = *reinterpret_cast<const float4*>(Dr + jb);
-                        dv[q * 4 + 0] = v.x;
-                        dv[q * 4 + 1] = v.y;
-                        dv[q * 4 + 2] = v.z;
-                        dv[q * 4 + 3] = v.w;
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            if (jb + e < n && jb + e > i) dv[q * 4 + e] = Dr[jb + e];
-                    }
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < NQ; ++q)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int x = q * 4 + e;
-                    const int64_t j = j0 + 4 * (c4 + q * LPR) + e;
-                    const bool valid = (j > i) && (j < n);
-                    float g[PG];
-                    sst += pair_term<P, LAT, GRAD>(zi, zj[x], dv[x], valid, p, D, g);
-                    if constexpr (GRAD) {
-#pragma unroll
-                        for (int c = 0; c < PG; ++c) {
-                            rowacc[c] += g[c];
-                            colacc[x][c] += g[c];
-                        }
-                    }
-                }
-        }
-        if constexpr (GRAD) {
-#pragma unroll
-            for (int c = 0; c < PG; ++c) {
-                const float tot = group_sum<LPR>(rowacc[c]);
-                if (c4 == 0 && i < n) D.rowpart[(lt * T + il) * PG + c] = tot;
-            }
-        }
-        sig.add(sst);
-    }
-
-    if constexpr (GRAD) {
-        // Column partials: RPS row groups hold partial sums for each column.
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int col = 4 * (c4 + q * LPR) + e;
+                const int x = q * 4 + e;
+                const int64_t j = j0 + 4 * (c4 + q * kLPR) + e;
+                const bool valid = !MASK || ((j > i) && (j < n) && (i < n));
+                float g[PG];
+                sst += pair_term<P, LAT, GRAD, MASK>(zi, zj[x], buf[q][e], valid, p, D, g);
+                if constexpr (GRAD) {
 #pragma unroll
-                for (int c = 0; c < PG; ++c) lds[(rr * T + col) * PG + c] = colacc[q * 4 + e][c];
+                    for (int c = 0; c < PG; ++c) {
+                        rowacc[c] += g[c];
+                        colacc[x][c] += g[c];
+                    }
+                }
             }
-        __syncthreads();
-        for (int x = tid; x < T * PG; x += kWG) {
-            float acc = 0.f;
-#pragma unroll 4
-            for (int r = 0; r < RPS; ++r) acc += lds[r * T * PG + x];
-            D.colpart[lt * T * PG + x] = acc;
-        }
-        __syncthreads();
-    }
-    // Stress of the tile: fixed-shape tree over the workgroup.
-    lds[tid] = sig.hi;
-    lds[kWG + tid] = sig.lo;
-    __syncthreads();
+        if constexpr (GRAD) {
 #pragma unroll
-    for (int st = kWG / 2; st > 0; st >>= 1) {
-        if (tid < st) {
-            Comp a;
-            a.hi = lds[tid];
-            a.lo = lds[kWG + tid];
-            Comp b;
-            b.hi = lds[tid + st];
-            b.lo = lds[kWG + tid + st];
-            a.add(b);
-            lds[tid] = a.hi;
-            lds[kWG + tid] = a.lo;
+            for (int c = 0; c < PG; ++c) {
+                const float tot = row16_sum(rowacc[c]);
+                if (c4 == 0 && (!MASK || i < n)) gpw(D.rowpart)[(lt * T + il) * PG + c] = tot;
+            }
         }
-        __syncthreads();
+        sig.add(sst);
+    };
+
+    f4v b0[NQ], b1[NQ];
+    load_step(0, b0);
+#pragma unroll
+    for (int s = 0; s < kUnitSteps; s += 2) {
+        if (s + 1 < kUnitSteps) load_step(s + 1, b1);
+        compute_step(s, b0);
+        if (s + 1 < kUnitSteps) {
+            if (s + 2 < kUnitSteps) load_step(s + 2, b0);
+            compute_step(s + 1, b1);
+        }
     }
-    if (tid == 0) {
-        D.sigpart[2 * lt + 0] = lds[0];
-        D.sigpart[2 * lt + 1] = lds[kWG];
+
+    if constexpr (GRAD) {
+        // column partials: the 16 row groups hold partial sums of each column
+#pragma unroll
+        for (int c = 0; c < PG; ++c) {
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) red[rr * T + 4 * (c4 + q * kLPR) + e] = colacc[q * 4 + e][c];
+            __syncthreads();
+            for (int x = tid; x < T; x += kWG) {
+                float acc = 0.f;
+#pragma unroll
+                for (int r = 0; r < kRPS; ++r) acc += red[r * T + x];
+                gpw(D.colpart)[((lt * UNITS + sub) * T + x) * PG + c] = acc;
+            }
+        }
     }
-    __syncthreads();
+    // stress: one compensated partial per wave (fixed butterfly, lane 0's copy)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        Comp other;
+        other.hi = __shfl_xor(sig.hi, o, 64);
+        other.lo = __shfl_xor(sig.lo, o, 64);
+        sig.add(other);
+    }
+    if ((tid & 63) == 0) {
+        const int64_t slot = (lt * UNITS + sub) * kWaves + (tid >> 6);
+        gpw(D.sigpart)[2 * slot + 0] = sig.hi;
+        gpw(D.sigpart)[2 * slot + 1] = sig.lo;
+    }
 }
 
-// Gradient of point k from the tile partials, in a fixed order: the row
-// partials of its tile row, then minus the column partials of its tile column.
+template <int P, int LAT, int T, bool GRAD>
+__device__ __forceinline__ void stress_unit(const InstDesc& D, int64_t lu, float* lds) {
+    constexpr int UNITS = TileShape<T>::UNITS;
+    const int64_t lt = lu / UNITS;
+    const int sub = (int)(lu % UNITS);
+    int64_t I, J;
+    tri_decode(lt, D.nb, I, J);
+    if (I * T + (int64_t)sub * kUR >= D.n) return;          // rows past n: nothing to do
+    const bool interior = D.vec && (I < J) && ((J + 1) * T <= D.n);
+    if (interior) unit_body<P, LAT, T, GRAD, false>(D, lt, sub, I, J, lds);
+    else unit_body<P, LAT, T, GRAD, true>(D, lt, sub, I, J, lds);
+}
+
+// Gradient of point k: row partials of its tile row, column partials of its
+// tile column (every unit of each tile), as kSplit interleaved Neumaier sums
+// -- this thread takes terms s, s + kSplit, ... -- combined later in index
+// order.  Row and column terms share one sequence: t < nrow are row terms.
 template <int P, int LAT, int T>
-__device__ __forceinline__ void reduce_point(const InstDesc& D, int64_t k, float (&G)[P]) {
+__device__ __forceinline__ void point_partial(const InstDesc& D, int64_t k, int s, Comp (&acc)[PG_<P, LAT>::value]) {
     constexpr int PG = PG_<P, LAT>::value;
+    constexpr int UNITS = TileShape<T>::UNITS;
     const int64_t b = k / T;
     const int64_t kl = k % T;
     const int64_t nb = D.nb;
-    Comp acc[PG];
-    for (int64_t J = b; J < nb; ++J) {
-        const int64_t lt = tri_index(b, J, nb);
+    const int64_t nrow = nb - b;
+    gfl* rp = gp(D.rowpart);
+    gfl* cp = gp(D.colpart);
+    // row terms t = s, s + kSplit, ...: loads of a batch in flight together,
+    // added in increasing t (an absent term adds an exact 0)
+    for (int64_t t0 = s; t0 < nrow; t0 += kSplit * kBatch) {
+        float v[kBatch][PG];
 #pragma unroll
-        for (int c = 0; c < PG; ++c) acc[c].add(D.rowpart[(lt * T + kl) * PG + c]);
-    }
-    for (int64_t I = 0; I <= b; ++I) {
-        const int64_t lt = tri_index(I, b, nb);
+        for (int q = 0; q < kBatch; ++q) {
+            const int64_t t = t0 + (int64_t)q * kSplit;
+            const int64_t lt = tri_index(b, b + t, nb);
 #pragma unroll
-        for (int c = 0; c < PG; ++c) acc[c].add(-D.colpart[(lt * T + kl) * PG + c]);
-    }
-    if constexpr (P == 2 && LAT == 0) {
-        const float v = acc[0].value();
-        G[0] = -v;
-        G[1] = v;
-    } else {
-#pragma unroll
-        for (int c = 0; c < P; ++c) G[c] = acc[c].value();
-    }
-}
-
-// Stress of instance D from its tile partials; executed by one whole workgroup.
-__device__ void reduce_sigma(const InstDesc& D, float* lds, float& hi, float& lo) {
-    const int tid = threadIdx.x;
-    const int64_t nt = tri_count(D.nb);
-    Comp acc;
-    for (int64_t t = tid; t < nt; t += kWG) {
-        Comp x;
-        x.hi = D.sigpart[2 * t];
-        x.lo = D.sigpart[2 * t + 1];
-        acc.add(x);
-    }
-    lds[tid] = acc.hi;
-    lds[kWG + tid] = acc.lo;
-    __syncthreads();
-    for (int st = kWG / 2; st > 0; st >>= 1) {
-        if (tid < st) {
-            Comp a;
-            a.hi = lds[tid];
-            a.lo = lds[kWG + tid];
-            Comp b;
-            b.hi = lds[tid + st];
-            b.lo = lds[kWG + tid + st];
-            a.add(b);
-            lds[tid] = a.hi;
-            lds[kWG + tid] = a.lo;
+            for (int c = 0; c < PG; ++c) v[q][c] = (t < nrow) ? rp[(lt * T + kl) * PG + c] : 0.f;
         }
-        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q)
+#pragma unroll
+            for (int c = 0; c < PG; ++c) acc[c].add(v[q][c]);
     }
-    hi = lds[0];
-    lo = lds[kWG];
+    // column terms follow the row terms in the same interleaving
+    const int64_t ncol = (b + 1) * UNITS;
+    const int64_t last_lt = tri_count(nb) - 1;
+    for (int64_t t0 = (s - nrow % kSplit + kSplit) % kSplit; t0 < ncol; t0 += kSplit * kBatch) {
+        float v[kBatch][PG];
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+            const int64_t t = t0 + (int64_t)q * kSplit;
+            const int64_t I = t / UNITS;
+            const int u = (int)(t % UNITS);
+            const int64_t lt = tri_index(I, b, nb);
+            // units past n (only in the last tile) were never written
+            const bool ok = (t < ncol) && !(lt == last_lt && I * T + (int64_t)u * kUR >= D.n);
+#pragma unroll
+            for (int c = 0; c < PG; ++c) v[q][c] = ok ? -cp[((lt * UNITS + u) * T + kl) * PG + c] : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q)
+#pragma unroll
+            for (int c = 0; c < PG; ++c) acc[c].add(v[q][c]);
+    }
+}
+
+// Combine the kSplit partial sums of each point (held in LDS) and apply the
+// result.  Threads are laid out as [kSplit][kWG / kSplit] points.
+template <int P, int LAT, int T>
+__device__ void apply_points(const InstDesc& D, int64_t k0, int mode, float* lds) {
+    constexpr int PG = PG_<P, LAT>::value;
+    constexpr int NPT = kWG / kSplit;
+    const int tid = threadIdx.x;
+    const int s = tid / NPT;
+    const int pl = tid % NPT;
+    const int64_t k = k0 + pl;
+    Comp acc[PG];
+    if (k < D.n) point_partial<P, LAT, T>(D, k, s, acc);
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < PG; ++c) {
+        lds[(c * kSplit + s) * NPT * 2 + 2 * pl] = acc[c].hi;
+        lds[(c * kSplit + s) * NPT * 2 + 2 * pl + 1] = acc[c].lo;
+    }
+    __syncthreads();
+    if (s == 0 && k < D.n) {
+        float G[P];
+        Comp tot[PG];
+#pragma unroll
+        for (int c = 0; c < PG; ++c)
+#pragma unroll
+            for (int q = 0; q < kSplit; ++q) {
+                Comp x;
+                x.hi = lds[(c * kSplit + q) * NPT * 2 + 2 * pl];
+                x.lo = lds[(c * kSplit + q) * NPT * 2 + 2 * pl + 1];
+                tot[c].add(x);
+            }
+        if constexpr (P == 2 && LAT == 0) {
+            const float v = 2.f * D.c2 * tot[0].value();
+            G[0] = -v;
+            G[1] = v;
+        } else {
+#pragma unroll
+            for (int c = 0; c < P; ++c) G[c] = 2.f * tot[c].value();
+        }
+        const int p = (P == kMaxP) ? D.p : P;
+        if (mode == kModeGrad) {
+            const float sc = D.grad_out ? *D.grad_out : 1.f;
+#pragma unroll
+            for (int c = 0; c < P; ++c)
+                if (c < p) D.gradZ[k * D.ldg + c] = sc * G[c];
+        } else {
+#pragma unroll
+            for (int c = 0; c < P; ++c)
+                if (c < p) D.Z[k * D.ldz + c] -= D.eta * G[c];
+        }
+    }
     __syncthreads();
 }
 
-// Map a global tile index to its instance (descriptors sorted by tile_off).
+// Stress of instance D from the per-wave unit partials (units past n, only in
+// the last tile, hold nothing), in kSigSlices contiguous slices: slice s is a
+// fixed-order sum (each thread takes every kWG-th partial, loads in batches,
+// then a fixed tree), and the stress is the slices added in index order.
+constexpr int kSigSlices = 16;
+
+template <int T>
+__device__ Comp sigma_slice(const InstDesc& D, int slice, float* lds) {
+    constexpr int UNITS = TileShape<T>::UNITS;
+    const int64_t nt = tri_count(D.nb);
+    const int64_t cnt = nt * UNITS * kWaves;
+    const int64_t a = cnt * slice / kSigSlices;
+    const int64_t e = cnt * (slice + 1) / kSigSlices;
+    gfl* sp = gp(D.sigpart);
+    Comp acc;
+    for (int64_t t0 = a + threadIdx.x; t0 < e; t0 += (int64_t)kWG * kBatch) {
+        float hv[kBatch], lv[kBatch];
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+            const int64_t t = t0 + (int64_t)q * kWG;
+            const int64_t lu = t / kWaves;
+            const int u = (int)(lu % UNITS);
+            const bool ok = (t < e) && !(lu / UNITS == nt - 1 && (D.nb - 1) * T + (int64_t)u * kUR >= D.n);
+            hv[q] = ok ? sp[2 * t] : 0.f;
+            lv[q] = ok ? sp[2 * t + 1] : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+            Comp x;
+            x.hi = hv[q];
+            x.lo = lv[q];
+            acc.add(x);
+        }
+    }
+    return wg_sum(acc, lds);
+}
+
+template <int T>
+__device__ Comp instance_sigma(const InstDesc& D, float* lds) {
+    Comp tot;
+    for (int sl = 0; sl < kSigSlices; ++sl) tot.add(sigma_slice<T>(D, sl, lds));
+    return tot;
+}
+
+__device__ __forceinline__ void write_sigma(const InstDesc& D, int mode, int it, const Comp& s) {
+    if (threadIdx.x != 0) return;
+    if (mode == kModeDescent) {
+        if (D.sigma_hist) D.sigma_hist[it] = s.hi + s.lo;
+    } else if (D.out_sigma) {
+        D.out_sigma[0] = s.hi;
+        D.out_sigma[1] = s.lo;
+    }
+}
+
+// Map a global unit index to its instance (descriptors sorted by tile_off,
+// which counts units).
 __device__ __forceinline__ int find_instance(const InstDesc* dd, int n_inst, int64_t q) {
     int lo = 0, hi = n_inst - 1;
     while (lo < hi) {
@@ -312,83 +504,87 @@ __device__ __forceinline__ int find_instance(const InstDesc* dd, int n_inst, int
 }
 
 template <int P, int LAT, int T, bool GRAD>
-__global__ __launch_bounds__(kWG) void k_stress_tiles(const InstDesc* __restrict__ dd, int n_inst, int64_t q_base) {
-    __shared__ float lds[tile_lds_floats<P, LAT, T>() > 2 * kWG ? tile_lds_floats<P, LAT, T>() : 2 * kWG];
+__global__ __launch_bounds__(kWG) void k_stress_units(const InstDesc* __restrict__ dd, int n_inst, int64_t q_base) {
+    __shared__ float lds[unit_lds_floats<P, T>()];
     const int64_t q = (int64_t)blockIdx.x + q_base;
     const int k = find_instance(dd, n_inst, q);
     const InstDesc D = dd[k];
-    stress_tile<P, LAT, T, GRAD>(D, q - D.tile_off, lds);
+    stress_unit<P, LAT, T, GRAD>(D, q - D.tile_off, lds);
 }
 
-// mode 0: write gradZ (scaled by *grad_out) and out_sigma; mode 1: descent
-// step Z -= eta G and sigma_hist[it]; mode 2: out_sigma only.  blockIdx.y =
-// instance; block nblk in x reduces the stress, blocks below it the points.
+// Reduction launch: blockIdx.y = instance; blocks 0 .. kSigSlices-1 sum one
+// slice of the stress each (the last of them to finish adds the slices, in
+// order), the following blocks take kWG / kSplit points each.
 template <int P, int LAT, int T>
 __global__ __launch_bounds__(kWG) void k_stress_reduce(const InstDesc* __restrict__ dd, int mode, int it) {
-    __shared__ float lds[2 * kWG];
+    constexpr int PG = PG_<P, LAT>::value;
+    constexpr int NPT = kWG / kSplit;
+    __shared__ float lds[2 * kSplit * NPT * PG > 2 * kWG ? 2 * kSplit * NPT * PG : 2 * kWG];
+    __shared__ int last;
     const InstDesc& D = dd[blockIdx.y];
-    const int64_t n = D.n;
-    const int64_t nblk = (n + kWG - 1) / kWG;
-    const int p = (P == kMaxP) ? D.p : P;
-    if ((int64_t)blockIdx.x == nblk) {
-        float hi, lo;
-        reduce_sigma(D, lds, hi, lo);
+    const int64_t nblk = (D.n + NPT - 1) / NPT;
+    if (blockIdx.x < kSigSlices) {
+        const Comp part = sigma_slice<T>(D, blockIdx.x, lds);
         if (threadIdx.x == 0) {
-            if (mode != 1) {
-                if (D.out_sigma) {
-                    D.out_sigma[0] = hi;
-                    D.out_sigma[1] = lo;
-                }
-            } else if (D.sigma_hist) {
-                D.sigma_hist[it] = hi + lo;
+            gpw(D.sigslice)[2 * blockIdx.x] = part.hi;
+            gpw(D.sigslice)[2 * blockIdx.x + 1] = part.lo;
+            __threadfence();
+            last = (atomicAdd(D.instcnt, 1u) + 1 == (uint32_t)kSigSlices) ? 1 : 0;
+        }
+        __syncthreads();
+        if (last && threadIdx.x == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            Comp tot;
+            for (int sl = 0; sl < kSigSlices; ++sl) {
+                Comp x;
+                x.hi = gp(D.sigslice)[2 * sl];
+                x.lo = gp(D.sigslice)[2 * sl + 1];
+                tot.add(x);
             }
+            write_sigma(D, mode, it, tot);
+            __hip_atomic_store(D.instcnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         return;
     }
-    if ((int64_t)blockIdx.x > nblk || mode == 2) return;
-    const int64_t k = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (k >= n) return;
-    float G[P];
-    reduce_point<P, LAT, T>(D, k, G);
-    if (mode == 0) {
-        const float sc = D.grad_out ? *D.grad_out : 1.f;
-#pragma unroll
-        for (int c = 0; c < P; ++c)
-            if (c < p) D.gradZ[k * D.ldg + c] = sc * G[c];
-    } else {
-#pragma unroll
-        for (int c = 0; c < P; ++c)
-            if (c < p) D.Z[k * D.ldz + c] -= D.eta * G[c];
-    }
+    if ((int64_t)(blockIdx.x - kSigSlices) >= nblk || mode == kModeSigma) return;
+    apply_points<P, LAT, T>(D, (int64_t)(blockIdx.x - kSigSlices) * NPT, mode, lds);
 }
 
-// Persistent solver.  Queue item q = (iteration it, instance k, local tile lt),
+__global__ void k_fill_u32(uint32_t* p, int64_t count, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+// Persistent solver.  Queue item q = (iteration it, instance k, local unit),
 // iteration-major, instances in the host's order.  A workgroup pops q, waits
 // until instance k has finished iteration it-1 (epoch[k] >= it), streams the
-// tile, and counts it done; the workgroup that completes the last tile of
-// (k, it) reduces the partials, takes the descent step, resets the counter and
-// publishes epoch[k] = it + 1.  Items are popped in queue order and every item
-// waits only on items popped before it, whose workgroups are already running,
-// so the queue drains whatever the number of resident workgroups.  A wait that
-// exceeds spin_limit ticks of the constant-rate device clock sets the abort status;
-// every workgroup then stops popping work and the kernel ends.
+// unit and counts it done (release fence, integer counter); the workgroup that
+// completes the last unit of (k, it) reduces the whole instance with the same
+// fixed-order sums as the reduction launch, takes the step, resets the counter
+// and publishes epoch[k] = it + 1.  Items are popped in queue order and every
+// item waits only on items popped before it, whose workgroups are already
+// running, so the queue drains whatever the number of resident workgroups.  A
+// wait longer than spin_limit ticks of the constant-rate device clock sets the
+// abort status; every workgroup then stops popping work and the kernel ends.
 template <int P, int LAT, int T>
 __global__ __launch_bounds__(kWG) void k_solve_persistent(const InstDesc* __restrict__ dd, int n_inst,
                                                           const int64_t* __restrict__ prefix,
                                                           int64_t per_iter, int iters, SolveCtl* ctl,
-                                                          uint32_t* cnt, uint32_t* epoch, int64_t spin_limit) {
-    constexpr int NL = tile_lds_floats<P, LAT, T>() > 2 * kWG ? tile_lds_floats<P, LAT, T>() : 2 * kWG;
-    __shared__ float lds[NL];
+                                                          uint32_t* epoch, int64_t spin_limit) {
+    constexpr int PG = PG_<P, LAT>::value;
+    constexpr int UNITS = TileShape<T>::UNITS;
+    constexpr int NL1 = unit_lds_floats<P, T>();
+    constexpr int NL2 = 2 * kSplit * (kWG / kSplit) * PG;
+    __shared__ float lds[NL1 > NL2 ? NL1 : NL2];
     __shared__ int64_t sh_q;
     __shared__ int sh_flag;
     const int tid = threadIdx.x;
     const int64_t total = per_iter * (int64_t)iters;
-    unsigned long long* head = &ctl->head;
     for (;;) {
         if (tid == 0) {
             const uint32_t st = __hip_atomic_load(&ctl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             int64_t q = total;
-            if (st == kStatusOk) q = (int64_t)atomicAdd(head, 1ull);
+            if (st == kStatusOk) q = (int64_t)atomicAdd(&ctl->head, 1ull);
             sh_q = q;
         }
         __syncthreads();
@@ -404,7 +600,7 @@ __global__ __launch_bounds__(kWG) void k_solve_persistent(const InstDesc* __rest
             else hi = mid - 1;
         }
         const int k = lo;
-        const int64_t lt = r - prefix[k];
+        const int64_t lu = r - prefix[k];
         if (tid == 0) {
             int ok = 1;
             if (__hip_atomic_load(&epoch[k], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < (uint32_t)it) {
@@ -432,31 +628,23 @@ __global__ __launch_bounds__(kWG) void k_solve_persistent(const InstDesc* __rest
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const InstDesc D = dd[k];
-        stress_tile<P, LAT, T, true>(D, lt, lds);
+        stress_unit<P, LAT, T, true>(D, lu, lds);
         __threadfence();
         __syncthreads();
         if (tid == 0) {
-            const uint32_t old = atomicAdd(&cnt[k], 1u);
-            sh_flag = (old + 1 == (uint32_t)tri_count(D.nb)) ? 1 : 0;
+            const uint32_t old = atomicAdd(D.instcnt, 1u);
+            sh_flag = (old + 1 == (uint32_t)(tri_count(D.nb) * UNITS)) ? 1 : 0;
         }
         __syncthreads();
         if (sh_flag) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            float shi, slo;
-            reduce_sigma(D, lds, shi, slo);
-            if (tid == 0 && D.sigma_hist) D.sigma_hist[it] = shi + slo;
-            const int p = (P == kMaxP) ? D.p : P;
-            for (int64_t pt = tid; pt < D.n; pt += kWG) {
-                float G[P];
-                reduce_point<P, LAT, T>(D, pt, G);
-#pragma unroll
-                for (int c = 0; c < P; ++c)
-                    if (c < p) D.Z[pt * D.ldz + c] -= D.eta * G[c];
-            }
+            const Comp s = instance_sigma<T>(D, lds);
+            write_sigma(D, kModeDescent, it, s);
+            for (int64_t k0 = 0; k0 < D.n; k0 += kWG / kSplit) apply_points<P, LAT, T>(D, k0, kModeDescent, lds);
             __threadfence();
             __syncthreads();
             if (tid == 0) {
-                __hip_atomic_store(&cnt[k], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(D.instcnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&epoch[k], (uint32_t)(it + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
@@ -465,72 +653,74 @@ __global__ __launch_bounds__(kWG) void k_solve_persistent(const InstDesc* __rest
 }
 
 // ------------------------------------------------------------- dispatch
-template <int P, int LAT, int T>
-static hipError_t tiles_impl(const InstDesc* dd, int n_inst, int64_t total, int64_t qb, bool grad, hipStream_t s) {
-    if (total <= 0) return hipSuccess;
-    if (grad)
-        hipLaunchKernelGGL((k_stress_tiles<P, LAT, T, true>), dim3((unsigned)total), dim3(kWG), 0, s, dd, n_inst, qb);
-    else
-        hipLaunchKernelGGL((k_stress_tiles<P, LAT, T, false>), dim3((unsigned)total), dim3(kWG), 0, s, dd, n_inst, qb);
-    return hipGetLastError();
-}
-
 static int p_bucket(int p) { return p <= 4 ? p : kMaxP; }
 
-template <int LAT, int T>
-static hipError_t tiles_p(const InstDesc* dd, int n_inst, int64_t total, int64_t qb, int p, bool grad,
-                          hipStream_t s) {
-    switch (p_bucket(p)) {
-        case 1: return tiles_impl<1, LAT, T>(dd, n_inst, total, qb, grad, s);
-        case 2: return tiles_impl<2, LAT, T>(dd, n_inst, total, qb, grad, s);
-        case 3: return tiles_impl<3, LAT, T>(dd, n_inst, total, qb, grad, s);
-        case 4: return tiles_impl<4, LAT, T>(dd, n_inst, total, qb, grad, s);
-        default: return tiles_impl<kMaxP, LAT, T>(dd, n_inst, total, qb, grad, s);
-    }
-}
-
-hipError_t launch_stress_tiles(const InstDesc* dd, int n_inst, int64_t count, int64_t q_base, int p, int latent,
-                               int T, bool grad, hipStream_t s) {
-    if (latent == 0) {
-        if (T == 64) return tiles_p<0, 64>(dd, n_inst, count, q_base, p, grad, s);
-        if (T == 128) return tiles_p<0, 128>(dd, n_inst, count, q_base, p, grad, s);
-        return tiles_p<0, 256>(dd, n_inst, count, q_base, p, grad, s);
-    }
-    if (T == 64) return tiles_p<1, 64>(dd, n_inst, count, q_base, p, grad, s);
-    if (T == 128) return tiles_p<1, 128>(dd, n_inst, count, q_base, p, grad, s);
-    return tiles_p<1, 256>(dd, n_inst, count, q_base, p, grad, s);
+template <int P, int LAT, int T>
+static hipError_t units_impl(const InstDesc* dd, int n_inst, int64_t count, int64_t qb, bool grad, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    if (grad)
+        hipLaunchKernelGGL((k_stress_units<P, LAT, T, true>), dim3((unsigned)count), dim3(kWG), 0, s, dd, n_inst, qb);
+    else
+        hipLaunchKernelGGL((k_stress_units<P, LAT, T, false>), dim3((unsigned)count), dim3(kWG), 0, s, dd, n_inst, qb);
+    return hipGetLastError();
 }
 
 template <int P, int LAT, int T>
 static hipError_t reduce_impl(const InstDesc* dd, int n_inst, int64_t max_n, int mode, int it, hipStream_t s) {
-    const unsigned gx = (unsigned)((max_n + kWG - 1) / kWG + 1);
+    const int64_t npt = kWG / kSplit;
+    const unsigned gx = (unsigned)((max_n + npt - 1) / npt + kSigSlices);
     hipLaunchKernelGGL((k_stress_reduce<P, LAT, T>), dim3(gx, (unsigned)n_inst), dim3(kWG), 0, s, dd, mode, it);
     return hipGetLastError();
 }
 
 template <int LAT, int T>
-static hipError_t reduce_p(const InstDesc* dd, int n_inst, int64_t max_n, int p, int mode, int it, hipStream_t s) {
+static hipError_t dispatch_p(int which, const InstDesc* dd, int n_inst, int64_t count, int64_t qb, int p, bool grad,
+                             int64_t max_n, int mode, int it, hipStream_t s) {
+#define GMDS_CALL(PP)                                                                 \
+    return which == 0 ? units_impl<PP, LAT, T>(dd, n_inst, count, qb, grad, s)         \
+                      : reduce_impl<PP, LAT, T>(dd, n_inst, max_n, mode, it, s);
     switch (p_bucket(p)) {
-        case 1: return reduce_impl<1, LAT, T>(dd, n_inst, max_n, mode, it, s);
-        case 2: return reduce_impl<2, LAT, T>(dd, n_inst, max_n, mode, it, s);
-        case 3: return reduce_impl<3, LAT, T>(dd, n_inst, max_n, mode, it, s);
-        case 4: return reduce_impl<4, LAT, T>(dd, n_inst, max_n, mode, it, s);
-        default: return reduce_impl<kMaxP, LAT, T>(dd, n_inst, max_n, mode, it, s);
+        case 1: GMDS_CALL(1)
+        case 2: GMDS_CALL(2)
+        case 3: GMDS_CALL(3)
+        case 4: GMDS_CALL(4)
+        default: GMDS_CALL(kMaxP)
     }
+#undef GMDS_CALL
+}
+
+template <int T>
+static hipError_t dispatch_lat(int which, const InstDesc* dd, int n_inst, int64_t count, int64_t qb, int p,
+                               int latent, bool grad, int64_t max_n, int mode, int it, hipStream_t s) {
+    if (latent == 0) return dispatch_p<0, T>(which, dd, n_inst, count, qb, p, grad, max_n, mode, it, s);
+    return dispatch_p<1, T>(which, dd, n_inst, count, qb, p, grad, max_n, mode, it, s);
+}
+
+static hipError_t dispatch(int which, const InstDesc* dd, int n_inst, int64_t count, int64_t qb, int p, int latent,
+                           int T, bool grad, int64_t max_n, int mode, int it, hipStream_t s) {
+    if (T == 64) return dispatch_lat<64>(which, dd, n_inst, count, qb, p, latent, grad, max_n, mode, it, s);
+    if (T == 128) return dispatch_lat<128>(which, dd, n_inst, count, qb, p, latent, grad, max_n, mode, it, s);
+    return dispatch_lat<256>(which, dd, n_inst, count, qb, p, latent, grad, max_n, mode, it, s);
+}
+
+hipError_t launch_stress_units(const InstDesc* dd, int n_inst, int64_t count, int64_t q_base, int p, int latent, int T,
+                               bool grad, hipStream_t s) {
+    return dispatch(0, dd, n_inst, count, q_base, p, latent, T, grad, 0, 0, 0, s);
 }
 
 hipError_t launch_stress_reduce(const InstDesc* dd, const InstDesc* hd, int n_inst, int p, int latent, int T,
                                 int mode, int it, hipStream_t s) {
     int64_t max_n = 0;
     for (int k = 0; k < n_inst; ++k) max_n = hd[k].n > max_n ? hd[k].n : max_n;
-    if (latent == 0) {
-        if (T == 64) return reduce_p<0, 64>(dd, n_inst, max_n, p, mode, it, s);
-        if (T == 128) return reduce_p<0, 128>(dd, n_inst, max_n, p, mode, it, s);
-        return reduce_p<0, 256>(dd, n_inst, max_n, p, mode, it, s);
-    }
-    if (T == 64) return reduce_p<1, 64>(dd, n_inst, max_n, p, mode, it, s);
-    if (T == 128) return reduce_p<1, 128>(dd, n_inst, max_n, p, mode, it, s);
-    return reduce_p<1, 256>(dd, n_inst, max_n, p, mode, it, s);
+    return dispatch(1, dd, n_inst, 0, 0, p, latent, T, true, max_n, mode, it, s);
+}
+
+int units_per_tile(int T) { return T / kUR; }
+
+hipError_t launch_fill_u32(uint32_t* ptr, int64_t count, uint32_t value, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, ptr, count, value);
+    return hipGetLastError();
 }
 
 template <int P, int LAT, int T>
@@ -565,14 +755,13 @@ int persistent_max_blocks_per_cu(int p, int latent, int T) {
     return nb > 0 ? nb : 1;
 }
 
-hipError_t launch_solve_persistent(const InstDesc* dd, int n_inst, const int64_t* d_tile_prefix,
-                                   int64_t tiles_per_iter, int iters, int p, int latent, int T, int grid,
-                                   SolveCtl* ctl, uint32_t* counters, uint32_t* epochs, int64_t spin_limit,
-                                   hipStream_t s) {
-    if (iters <= 0 || tiles_per_iter <= 0) return hipSuccess;
+hipError_t launch_solve_persistent(const InstDesc* dd, int n_inst, const int64_t* d_unit_prefix,
+                                   int64_t units_per_iter, int iters, int p, int latent, int T, int grid,
+                                   SolveCtl* ctl, uint32_t* epochs, int64_t spin_limit, hipStream_t s) {
+    if (iters <= 0 || units_per_iter <= 0) return hipSuccess;
     const void* fn = persistent_ptr(p, latent, T);
-    void* args[] = {(void*)&dd, (void*)&n_inst, (void*)&d_tile_prefix, (void*)&tiles_per_iter, (void*)&iters,
-                    (void*)&ctl, (void*)&counters, (void*)&epochs, (void*)&spin_limit};
+    void* args[] = {(void*)&dd, (void*)&n_inst, (void*)&d_unit_prefix, (void*)&units_per_iter, (void*)&iters,
+                    (void*)&ctl, (void*)&epochs, (void*)&spin_limit};
     return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kWG), args, 0, s);
 }
 

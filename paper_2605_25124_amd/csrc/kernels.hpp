@@ -8,6 +8,7 @@ namespace gmds {
 
 constexpr int kMaxP = 8;           // latent dimensions supported by the stress kernels
 constexpr int kMaxNu = 64;         // nu values per gini_dissim call
+constexpr int kStressWaves = 4;    // waves per stress workgroup (one stress partial each)
 
 // Per-instance description of one stress evaluation / descent problem.
 // Built on the host, read by the kernels.
@@ -18,17 +19,26 @@ struct InstDesc {
     float* gradZ;          // n x p gradient output (single evaluation), or nullptr
     const float* grad_out; // device scalar multiplying gradZ, or nullptr
     float* out_sigma;      // device (hi, lo), or nullptr
-    float* rowpart;        // scratch: [ntiles][T][pg] row partial gradients
-    float* colpart;        // scratch: [ntiles][T][pg] column partial gradients
-    float* sigpart;        // scratch: [ntiles][2] partial stress (hi, lo)
+    float* rowpart;        // scratch: [ntiles][T][pg] row partial gradients (one per row and tile)
+    float* colpart;        // scratch: [ntiles][units][T][pg] column partial gradients (one per unit)
+    float* sigpart;        // scratch: [ntiles][units][kStressWaves][2] partial stress (hi, lo) per wave
+    float* sigslice;       // scratch: [16][2] stress slices of the reduction launch
+    uint32_t* instcnt;     // [1] finished stress slices / units; zero between launches
     int64_t n, ldd, ldz, ldg;
     int64_t nb;            // tiles per side = ceil(n / T)
-    int64_t tile_off;      // first global tile index of this instance
+    int64_t tile_off;      // first global work unit of this instance
     int32_t p;
     int32_t vec;           // Delta rows 16-byte aligned and ldd % 4 == 0
     float eta;             // descent step
     float c2;              // p = 2 Gini latent: 2^(1-nu)
     float wtab[2 * kMaxP - 1];  // Gini latent: (p/2) W_{p,nu}[t], t = 2 .. 2p
+};
+
+// What a stress launch produces once every tile of an instance is done.
+enum StressMode : int {
+    kModeGrad = 0,      // gradZ (scaled by *grad_out) and out_sigma
+    kModeDescent = 1,   // Z -= eta * grad and sigma_hist[it]
+    kModeSigma = 2      // out_sigma only (no gradient work)
 };
 
 // Device-side status word of a persistent solve.
@@ -56,20 +66,22 @@ hipError_t launch_rank(const float* V, int64_t rows, int d, int64_t ldv, int32_t
 
 hipError_t launch_dissim(const DissimArgs& a, hipStream_t s);
 
-// Evaluate global tiles q_base .. q_base+count-1 of the n_inst instances
-// described by `dd` (device; sorted by tile_off).
-hipError_t launch_stress_tiles(const InstDesc* dd, int n_inst, int64_t count, int64_t q_base, int p, int latent,
-                               int T, bool grad, hipStream_t s);
-// Reduce tile partials: mode 0 writes gradZ and out_sigma, mode 1 takes a
-// descent step and records sigma_hist[it], mode 2 writes out_sigma only.
-hipError_t launch_stress_reduce(const InstDesc* dd, const InstDesc* hd, int n_inst, int p, int latent,
-                                int T, int mode, int it, hipStream_t s);
-// One launch: all instances, all iterations.
-hipError_t launch_solve_persistent(const InstDesc* dd, int n_inst, const int64_t* d_tile_prefix,
-                                   int64_t tiles_per_iter, int iters, int p, int latent, int T, int grid,
-                                   SolveCtl* ctl, uint32_t* counters, uint32_t* epochs, int64_t spin_limit,
-                                   hipStream_t s);
+// Stream global work units q_base .. q_base+count-1 of the n_inst instances
+// described by `dd` (device; sorted by tile_off): tile partials only.
+hipError_t launch_stress_units(const InstDesc* dd, int n_inst, int64_t count, int64_t q_base, int p, int latent, int T,
+                               bool grad, hipStream_t s);
+// Reduce the partials of every instance (`hd` is the host copy of `dd`):
+// StressMode says what is produced; `it` indexes sigma_hist in descent mode.
+hipError_t launch_stress_reduce(const InstDesc* dd, const InstDesc* hd, int n_inst, int p, int latent, int T,
+                                int mode, int it, hipStream_t s);
+int units_per_tile(int T);
+// One launch: all instances, all iterations of the descent.
+hipError_t launch_solve_persistent(const InstDesc* dd, int n_inst, const int64_t* d_unit_prefix,
+                                   int64_t units_per_iter, int iters, int p, int latent, int T, int grid,
+                                   SolveCtl* ctl, uint32_t* epochs, int64_t spin_limit, hipStream_t s);
 int persistent_max_blocks_per_cu(int p, int latent, int T);
+// Set `count` words to `value` (counters, epochs).
+hipError_t launch_fill_u32(uint32_t* ptr, int64_t count, uint32_t value, hipStream_t s);
 
 // Gradient components the stress kernels store per point in the tile
 // partials: the p = 2 Gini gradient is (-g, g), so one; p <= 4 has its own
