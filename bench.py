@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--mode", choices=["auto", "persistent", "batched"], default="auto")
     ap.add_argument("--tile", type=int, default=256)
+    ap.add_argument("--sweep-mode", choices=["auto", "persistent", "batched"], default="auto")
+    ap.add_argument("--sweep-tile", type=int, default=0)
     return ap.parse_args()
 
 
@@ -104,21 +106,25 @@ def main():
     gm.gini_mds_solve([inst(Zw)], args.warmup, best["flags"], best["tile"], best["grid"])
     torch.cuda.synchronize()
 
-    # ---- timed region: K descent steps
+    # ---- timed region: K descent steps (no instrumentation inside)
     Z = Z0.clone()
     hist = torch.zeros(args.steps, device=dev)
-    gm.gini_profile_enable(0, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     gm.gini_mds_solve([inst(Z, hist)], args.steps, best["flags"], best["tile"], best["grid"])
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    prof = gm.gini_profile_read(0)
-    gm.gini_profile_enable(0, False)
     ms_step = el * 1e3 / args.steps
     value = pairs / (el / args.steps)
     h = hist.cpu().numpy()
     log(f"{args.steps} steps: {ms_step * 1e3:.1f} us/step, sigma {h[0]:.6e} -> {h[-1]:.6e}")
+    # ---- the same K steps again with HIP events around every launch (per-kernel times)
+    Z = Z0.clone()
+    gm.gini_profile_enable(0, True)
+    gm.gini_mds_solve([inst(Z)], args.steps, best["flags"], best["tile"], best["grid"])
+    torch.cuda.synchronize()
+    prof = gm.gini_profile_read(0)
+    gm.gini_profile_enable(0, False)
 
     # dominant kernel and its algorithmic traffic per launch
     alg_bytes = 4.0 * pairs + 4.0 * n * p + 4.0 * n * p
@@ -158,7 +164,11 @@ def main():
         def insts():
             return [gm.Instance(Ds[k], Z0s[k].clone(), nus[k]) for k in range(n_inst)]
 
-        tuned = gm.gini_autotune(insts(), 3)
+        if args.sweep_mode == "auto":
+            tuned = gm.gini_autotune(insts(), 3)
+        else:
+            tuned = {"flags": gm.SOLVE_PERSISTENT if args.sweep_mode == "persistent" else gm.SOLVE_BATCHED,
+                     "tile": args.sweep_tile or 64, "grid": 0}
         log(f"sweep: {n_inst} instances, build {sweep_build:.2f} s, tuned {tuned}")
         I1 = insts()
         gm.gini_mds_solve(I1, 5, tuned["flags"], tuned["tile"], tuned["grid"])

@@ -391,6 +391,8 @@ gini_status stress_common(gini_ctx* c, const float* Delta, int64_t n, int64_t ld
     if (st != GINI_OK) return st;
     D.instcnt = c->cnt;
     D.tile_off = 0;
+    D.red_off = 0;
+    const int64_t rblocks = gmds::reduce_block_count(D.n, D.nb, T);
     void* dd = nullptr;
     Slot* sl = nullptr;
     st = upload(c, &D, sizeof D, s, &dd, &sl);
@@ -402,8 +404,8 @@ gini_status stress_common(gini_ctx* c, const float* Delta, int64_t n, int64_t ld
     }
     {
         ProfScope ps(c, kProfReduce, s);
-        GINI_HIP(c, gmds::launch_stress_reduce(ddp, &D, 1, p, latent, T, grad ? gmds::kModeGrad : gmds::kModeSigma,
-                                               0, s));
+        GINI_HIP(c, gmds::launch_stress_reduce(ddp, 1, rblocks, 0, p, latent, T,
+                                               grad ? gmds::kModeGrad : gmds::kModeSigma, 0, s));
     }
     return slot_done(c, sl, s);
 }
@@ -412,8 +414,9 @@ gini_status stress_common(gini_ctx* c, const float* Delta, int64_t n, int64_t ld
 struct Plan {
     std::vector<InstDesc> desc;     // in queue (LPT) order
     std::vector<int> order;         // desc[k] is caller instance order[k]
-    std::vector<int64_t> prefix;    // tile prefix, n_inst + 1
-    int64_t tiles = 0;
+    std::vector<int64_t> prefix;    // work-unit prefix, n_inst + 1
+    int64_t tiles = 0;              // work units per iteration
+    int64_t rblocks = 0;            // reduction blocks per iteration
     int p = 0, latent = 0, T = 0;
 };
 
@@ -472,6 +475,8 @@ gini_status make_plan(gini_ctx* c, const gini_instance* inst, int32_t n_inst, in
         const int64_t nt = layout(D, T);
         D.tile_off = P.prefix[k];
         P.prefix[k + 1] = P.prefix[k] + nt;
+        D.red_off = P.rblocks;
+        P.rblocks += gmds::reduce_block_count(D.n, D.nb, T);
         floats += partial_floats(D, T, pg);
         floats = (floats + 63) & ~size_t(63);
     }
@@ -523,8 +528,10 @@ gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStr
                                                           true, s));
                 }
                 ProfScope ps(c, kProfReduce, s);
-                GINI_HIP(c, gmds::launch_stress_reduce(ddp + k, &P.desc[k], 1, P.p, P.latent, P.T,
-                                                       gmds::kModeDescent, it, s));
+                GINI_HIP(c, gmds::launch_stress_reduce(ddp + k, 1,
+                                                       gmds::reduce_block_count(P.desc[k].n, P.desc[k].nb, P.T),
+                                                       P.desc[k].red_off, P.p, P.latent, P.T, gmds::kModeDescent, it,
+                                                       s));
             }
         }
     } else if (mode == GINI_SOLVE_BATCHED) {
@@ -534,7 +541,7 @@ gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStr
                 GINI_HIP(c, gmds::launch_stress_units(ddp, n_inst, P.tiles, 0, P.p, P.latent, P.T, true, s));
             }
             ProfScope ps(c, kProfReduce, s);
-            GINI_HIP(c, gmds::launch_stress_reduce(ddp, P.desc.data(), n_inst, P.p, P.latent, P.T,
+            GINI_HIP(c, gmds::launch_stress_reduce(ddp, n_inst, P.rblocks, 0, P.p, P.latent, P.T,
                                                    gmds::kModeDescent, it, s));
         }
     } else {

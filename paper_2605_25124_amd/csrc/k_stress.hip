@@ -438,18 +438,31 @@ __device__ void apply_points(const InstDesc& D, int64_t k0, int mode, float* lds
 }
 
 // Stress of instance D from the per-wave unit partials (units past n, only in
-// the last tile, hold nothing), in kSigSlices contiguous slices: slice s is a
-// fixed-order sum (each thread takes every kWG-th partial, loads in batches,
-// then a fixed tree), and the stress is the slices added in index order.
+// the last tile, hold nothing), in contiguous slices: slice s is a fixed-order
+// sum (each thread takes every kWG-th partial, loads in batches, then a fixed
+// tree), and the stress is the slices added in index order.
 constexpr int kSigSlices = 16;
+
+template <int T>
+__device__ __forceinline__ int64_t sigma_count(const InstDesc& D) {
+    return tri_count(D.nb) * TileShape<T>::UNITS * kWaves;
+}
+// Slices of the stress sum: about 4096 partials each, at most kSigSlices (one
+// slice -- written directly, no combining step -- for small instances).
+template <int T>
+__device__ __forceinline__ int sigma_slices(const InstDesc& D) {
+    const int64_t s = sigma_count<T>(D) / 4096;
+    return (int)(s < 1 ? 1 : (s > kSigSlices ? kSigSlices : s));
+}
 
 template <int T>
 __device__ Comp sigma_slice(const InstDesc& D, int slice, float* lds) {
     constexpr int UNITS = TileShape<T>::UNITS;
     const int64_t nt = tri_count(D.nb);
-    const int64_t cnt = nt * UNITS * kWaves;
-    const int64_t a = cnt * slice / kSigSlices;
-    const int64_t e = cnt * (slice + 1) / kSigSlices;
+    const int64_t cnt = sigma_count<T>(D);
+    const int ns = sigma_slices<T>(D);
+    const int64_t a = cnt * slice / ns;
+    const int64_t e = cnt * (slice + 1) / ns;
     gfl* sp = gp(D.sigpart);
     Comp acc;
     for (int64_t t0 = a + threadIdx.x; t0 < e; t0 += (int64_t)kWG * kBatch) {
@@ -476,8 +489,10 @@ __device__ Comp sigma_slice(const InstDesc& D, int slice, float* lds) {
 
 template <int T>
 __device__ Comp instance_sigma(const InstDesc& D, float* lds) {
+    const int ns = sigma_slices<T>(D);
+    if (ns == 1) return sigma_slice<T>(D, 0, lds);
     Comp tot;
-    for (int sl = 0; sl < kSigSlices; ++sl) tot.add(sigma_slice<T>(D, sl, lds));
+    for (int sl = 0; sl < ns; ++sl) tot.add(sigma_slice<T>(D, sl, lds));
     return tot;
 }
 
@@ -512,30 +527,52 @@ __global__ __launch_bounds__(kWG) void k_stress_units(const InstDesc* __restrict
     stress_unit<P, LAT, T, GRAD>(D, q - D.tile_off, lds);
 }
 
-// Reduction launch: blockIdx.y = instance; blocks 0 .. kSigSlices-1 sum one
-// slice of the stress each (the last of them to finish adds the slices, in
-// order), the following blocks take kWG / kSplit points each.
+// Number of reduction blocks of an instance: its stress slices, then one
+// block per kWG / kSplit points.
+template <int T>
+__device__ __forceinline__ int64_t reduce_blocks(const InstDesc& D) {
+    return sigma_slices<T>(D) + (D.n + kWG / kSplit - 1) / (kWG / kSplit);
+}
+
+// Reduction launch over the concatenated blocks of all instances (block
+// offsets in red_off).  The first blocks of an instance sum one slice of its
+// stress each (with several slices, the last to finish adds them in order);
+// the following blocks take kWG / kSplit points each.
 template <int P, int LAT, int T>
-__global__ __launch_bounds__(kWG) void k_stress_reduce(const InstDesc* __restrict__ dd, int mode, int it) {
+__global__ __launch_bounds__(kWG) void k_stress_reduce(const InstDesc* __restrict__ dd, int n_inst, int64_t q_base,
+                                                       int mode, int it) {
     constexpr int PG = PG_<P, LAT>::value;
     constexpr int NPT = kWG / kSplit;
     __shared__ float lds[2 * kSplit * NPT * PG > 2 * kWG ? 2 * kSplit * NPT * PG : 2 * kWG];
     __shared__ int last;
-    const InstDesc& D = dd[blockIdx.y];
-    const int64_t nblk = (D.n + NPT - 1) / NPT;
-    if (blockIdx.x < kSigSlices) {
-        const Comp part = sigma_slice<T>(D, blockIdx.x, lds);
+    const int64_t q = (int64_t)blockIdx.x + q_base;
+    int lo = 0, hi = n_inst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (dd[mid].red_off <= q) lo = mid;
+        else hi = mid - 1;
+    }
+    const InstDesc& D = dd[lo];
+    const int64_t b = q - D.red_off;
+    const int ns = sigma_slices<T>(D);
+    if (b < ns) {
+        const Comp part = sigma_slice<T>(D, (int)b, lds);
         if (threadIdx.x == 0) {
-            gpw(D.sigslice)[2 * blockIdx.x] = part.hi;
-            gpw(D.sigslice)[2 * blockIdx.x + 1] = part.lo;
-            __threadfence();
-            last = (atomicAdd(D.instcnt, 1u) + 1 == (uint32_t)kSigSlices) ? 1 : 0;
+            if (ns == 1) {
+                write_sigma(D, mode, it, part);
+            } else {
+                gpw(D.sigslice)[2 * b] = part.hi;
+                gpw(D.sigslice)[2 * b + 1] = part.lo;
+                __threadfence();
+                last = (atomicAdd(D.instcnt, 1u) + 1 == (uint32_t)ns) ? 1 : 0;
+            }
         }
+        if (ns == 1) return;
         __syncthreads();
         if (last && threadIdx.x == 0) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             Comp tot;
-            for (int sl = 0; sl < kSigSlices; ++sl) {
+            for (int sl = 0; sl < ns; ++sl) {
                 Comp x;
                 x.hi = gp(D.sigslice)[2 * sl];
                 x.lo = gp(D.sigslice)[2 * sl + 1];
@@ -546,8 +583,8 @@ __global__ __launch_bounds__(kWG) void k_stress_reduce(const InstDesc* __restric
         }
         return;
     }
-    if ((int64_t)(blockIdx.x - kSigSlices) >= nblk || mode == kModeSigma) return;
-    apply_points<P, LAT, T>(D, (int64_t)(blockIdx.x - kSigSlices) * NPT, mode, lds);
+    if (mode == kModeSigma) return;
+    apply_points<P, LAT, T>(D, (b - ns) * NPT, mode, lds);
 }
 
 __global__ void k_fill_u32(uint32_t* p, int64_t count, uint32_t v) {
@@ -666,10 +703,11 @@ static hipError_t units_impl(const InstDesc* dd, int n_inst, int64_t count, int6
 }
 
 template <int P, int LAT, int T>
-static hipError_t reduce_impl(const InstDesc* dd, int n_inst, int64_t max_n, int mode, int it, hipStream_t s) {
-    const int64_t npt = kWG / kSplit;
-    const unsigned gx = (unsigned)((max_n + npt - 1) / npt + kSigSlices);
-    hipLaunchKernelGGL((k_stress_reduce<P, LAT, T>), dim3(gx, (unsigned)n_inst), dim3(kWG), 0, s, dd, mode, it);
+static hipError_t reduce_impl(const InstDesc* dd, int n_inst, int64_t blocks, int64_t qb, int mode, int it,
+                              hipStream_t s) {
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_stress_reduce<P, LAT, T>), dim3((unsigned)blocks), dim3(kWG), 0, s, dd, n_inst, qb, mode,
+                       it);
     return hipGetLastError();
 }
 
@@ -678,7 +716,7 @@ static hipError_t dispatch_p(int which, const InstDesc* dd, int n_inst, int64_t 
                              int64_t max_n, int mode, int it, hipStream_t s) {
 #define GMDS_CALL(PP)                                                                 \
     return which == 0 ? units_impl<PP, LAT, T>(dd, n_inst, count, qb, grad, s)         \
-                      : reduce_impl<PP, LAT, T>(dd, n_inst, max_n, mode, it, s);
+                      : reduce_impl<PP, LAT, T>(dd, n_inst, max_n, qb, mode, it, s);  /* max_n: block count */
     switch (p_bucket(p)) {
         case 1: GMDS_CALL(1)
         case 2: GMDS_CALL(2)
@@ -708,11 +746,17 @@ hipError_t launch_stress_units(const InstDesc* dd, int n_inst, int64_t count, in
     return dispatch(0, dd, n_inst, count, q_base, p, latent, T, grad, 0, 0, 0, s);
 }
 
-hipError_t launch_stress_reduce(const InstDesc* dd, const InstDesc* hd, int n_inst, int p, int latent, int T,
-                                int mode, int it, hipStream_t s) {
-    int64_t max_n = 0;
-    for (int k = 0; k < n_inst; ++k) max_n = hd[k].n > max_n ? hd[k].n : max_n;
-    return dispatch(1, dd, n_inst, 0, 0, p, latent, T, true, max_n, mode, it, s);
+hipError_t launch_stress_reduce(const InstDesc* dd, int n_inst, int64_t blocks, int64_t q_base, int p, int latent,
+                                int T, int mode, int it, hipStream_t s) {
+    return dispatch(1, dd, n_inst, 0, q_base, p, latent, T, true, blocks, mode, it, s);
+}
+
+// Host mirror of reduce_blocks (must agree with the device functions above).
+int64_t reduce_block_count(int64_t n, int64_t nb, int T) {
+    const int64_t cnt = tri_count(nb) * (T / kUR) * kWaves;
+    int64_t ns = cnt / 4096;
+    ns = ns < 1 ? 1 : (ns > kSigSlices ? kSigSlices : ns);
+    return ns + (n + kWG / kSplit - 1) / (kWG / kSplit);
 }
 
 int units_per_tile(int T) { return T / kUR; }

@@ -27,6 +27,7 @@ struct InstDesc {
     int64_t n, ldd, ldz, ldg;
     int64_t nb;            // tiles per side = ceil(n / T)
     int64_t tile_off;      // first global work unit of this instance
+    int64_t red_off;       // first block of this instance in a reduction launch
     int32_t p;
     int32_t vec;           // Delta rows 16-byte aligned and ldd % 4 == 0
     float eta;             // descent step
@@ -70,10 +71,13 @@ hipError_t launch_dissim(const DissimArgs& a, hipStream_t s);
 // described by `dd` (device; sorted by tile_off): tile partials only.
 hipError_t launch_stress_units(const InstDesc* dd, int n_inst, int64_t count, int64_t q_base, int p, int latent, int T,
                                bool grad, hipStream_t s);
-// Reduce the partials of every instance (`hd` is the host copy of `dd`):
-// StressMode says what is produced; `it` indexes sigma_hist in descent mode.
-hipError_t launch_stress_reduce(const InstDesc* dd, const InstDesc* hd, int n_inst, int p, int latent, int T,
-                                int mode, int it, hipStream_t s);
+// Reduce the partials of every instance; `blocks` is the sum over instances
+// of reduce_block_count (instances sorted by red_off); blocks are numbered
+// from q_base.  StressMode says what
+// is produced; `it` indexes sigma_hist in descent mode.
+hipError_t launch_stress_reduce(const InstDesc* dd, int n_inst, int64_t blocks, int64_t q_base, int p, int latent,
+                                int T, int mode, int it, hipStream_t s);
+int64_t reduce_block_count(int64_t n, int64_t nb, int T);
 int units_per_tile(int T);
 // One launch: all instances, all iterations of the descent.
 hipError_t launch_solve_persistent(const InstDesc* dd, int n_inst, const int64_t* d_unit_prefix,
