@@ -95,7 +95,7 @@ def main():
         return gm.Instance(D, Z, nu, gm.LATENT_GINI, 0.0, hist)
 
     if args.mode == "auto":
-        best = gm.gini_autotune([inst(Z0.clone())], 3)
+        best = gm.gini_autotune([inst(Z0.clone())], 10)
     else:
         best = {"flags": gm.SOLVE_PERSISTENT if args.mode == "persistent" else gm.SOLVE_BATCHED,
                 "tile": args.tile, "grid": 0}
@@ -165,7 +165,7 @@ def main():
             return [gm.Instance(Ds[k], Z0s[k].clone(), nus[k]) for k in range(n_inst)]
 
         if args.sweep_mode == "auto":
-            tuned = gm.gini_autotune(insts(), 3)
+            tuned = gm.gini_autotune(insts(), 10)
         else:
             tuned = {"flags": gm.SOLVE_PERSISTENT if args.sweep_mode == "persistent" else gm.SOLVE_BATCHED,
                      "tile": args.sweep_tile or 64, "grid": 0}

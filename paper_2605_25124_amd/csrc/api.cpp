@@ -597,7 +597,7 @@ gini_status solve_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst, c
 
 gini_status autotune_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst, int32_t probe_iters,
                           gini_solve_opts* best, hipStream_t s) {
-    if (probe_iters < 1) probe_iters = 3;
+    if (probe_iters < 1) probe_iters = 8;
     struct ProfPause {
         gini_ctx* c;
         bool was;
@@ -636,8 +636,10 @@ gini_status autotune_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst
     }
     float best_ms = 1e30f;
     gini_solve_opts best_o{0, GINI_SOLVE_PERSISTENT, 0, 0};
+    constexpr int kReps = 4;                                   // first run warms up; best of the rest
     for (size_t ci = 0; ci < cand.size() && st == GINI_OK; ++ci) {
-        for (int rep = 0; rep < 2 && st == GINI_OK; ++rep) {   // first run warms up
+        float cand_ms = 1e30f;
+        for (int rep = 0; rep < kReps && st == GINI_OK; ++rep) {
             for (int k = 0; k < n_inst && st == GINI_OK; ++k) {
                 const size_t bytes = (size_t)((inst[k].n - 1) * inst[k].ldz + inst[k].p) * sizeof(float);
                 if (hipMemcpyAsync(zcopy[k], inst[k].Z, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
@@ -650,10 +652,11 @@ gini_status autotune_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst
             (void)hipEventSynchronize(e1);
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, e0, e1);
-            if (st == GINI_OK && rep == 1 && ms < best_ms) {
-                best_ms = ms;
-                best_o = cand[ci];
-            }
+            if (st == GINI_OK && rep > 0 && ms < cand_ms) cand_ms = ms;
+        }
+        if (st == GINI_OK && cand_ms < best_ms) {
+            best_ms = cand_ms;
+            best_o = cand[ci];
         }
     }
     (void)hipStreamSynchronize(s);
@@ -676,7 +679,7 @@ gini_status solve_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst, c
         auto it = c->tune.find(key);
         gini_solve_opts t{};
         if (it == c->tune.end()) {
-            gini_status st = autotune_impl(c, inst, n_inst, 3, &t, s);
+            gini_status st = autotune_impl(c, inst, n_inst, 8, &t, s);
             if (st != GINI_OK) return st;
         } else {
             t = it->second.opts;

@@ -33,7 +33,7 @@ constexpr int kRPS = kWG / kLPR;         // rows per step
 constexpr int kUR = 64;                  // rows per work unit
 constexpr int kUnitSteps = kUR / kRPS;   // steps per unit
 constexpr int kSplit = 16;               // interleaved partial sums per point in the reduction
-constexpr int kBatch = 4;                // loads in flight per partial sum
+constexpr int kBatch = 8;                // loads in flight per partial sum
 constexpr int kWaves = kStressWaves;     // waves per workgroup (one stress partial each)
 static_assert(kWaves * 64 == kWG, "one stress partial per wave");
 
@@ -157,11 +157,11 @@ __device__ Comp wg_sum(Comp v, float* lds) {
     return r;
 }
 
-// LDS floats used by one unit: the latent rows of the unit, the column
-// reduction (16 row groups x T) and the stress tree.
+// LDS floats used by one unit: the latent rows and columns of the unit, the
+// column reduction (16 row groups x T) and the stress tree.
 template <int P, int T>
 constexpr int unit_lds_floats() {
-    return kUR * P + (kRPS * T > 2 * kWG ? kRPS * T : 2 * kWG);
+    return kUR * P + T * P + (kRPS * T > 2 * kWG ? kRPS * T : 2 * kWG);
 }
 
 // Stream unit `sub` (rows I*T + sub*UR ..) of tile lt = (I, J) of instance D:
@@ -182,33 +182,35 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
     const int p = (P == kMaxP) ? D.p : P;
     gfl* Zg = gp(D.Z);
     float* zrow = lds;                                  // [kUR][P]
-    float* red = lds + kUR * P;
+    float* zcol = lds + kUR * P;                        // [T][P]
+    float* red = zcol + T * P;
 
-    // latent rows of this unit into LDS; latent columns into registers
+    // latent rows and columns of this unit into LDS (coalesced), then the
+    // thread's columns into registers
     for (int x = tid; x < kUR * P; x += kWG) {
         const int r = x / P, c = x % P;
         const int64_t i = i0 + r;
         zrow[x] = (c < p && (!MASK || i < n)) ? Zg[i * D.ldz + c] : 0.f;
     }
+    for (int x = tid; x < T * P; x += kWG) {
+        const int r = x / P, c = x % P;
+        const int64_t j = j0 + r;
+        zcol[x] = (c < p && (!MASK || j < n)) ? Zg[j * D.ldz + c] : 0.f;
+    }
+    __syncthreads();
     float zj[CPT][P];
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int64_t j = j0 + 4 * (c4 + q * kLPR) + e;
+        for (int e = 0; e < 4; ++e)
 #pragma unroll
-            for (int c = 0; c < P; ++c) {
-                if constexpr (MASK) zj[q * 4 + e][c] = (j < n && c < p) ? Zg[j * D.ldz + c] : 0.f;
-                else zj[q * 4 + e][c] = (c < p) ? Zg[j * D.ldz + c] : 0.f;
-            }
-        }
+            for (int c = 0; c < P; ++c) zj[q * 4 + e][c] = zcol[(4 * (c4 + q * kLPR) + e) * P + c];
     float colacc[CPT][PG];
 #pragma unroll
     for (int x = 0; x < CPT; ++x)
 #pragma unroll
         for (int c = 0; c < PG; ++c) colacc[x][c] = 0.f;
     Comp sig;
-    __syncthreads();
 
     // Delta loads for one step of the unit (unmasked: 16-byte global loads)
     auto load_step = [&](int s, f4v (&buf)[NQ]) {
@@ -341,40 +343,32 @@ __device__ __forceinline__ void point_partial(const InstDesc& D, int64_t k, int 
     const int64_t b = k / T;
     const int64_t kl = k % T;
     const int64_t nb = D.nb;
-    const int64_t nrow = nb - b;
+    const int64_t nrow = nb - b;                       // row partials: tiles (b, b..nb-1)
+    const int64_t nterm = nrow + (b + 1) * UNITS;      // then column partials: units of tiles (0..b, b)
+    const int64_t last_lt = tri_count(nb) - 1;
     gfl* rp = gp(D.rowpart);
     gfl* cp = gp(D.colpart);
-    // row terms t = s, s + kSplit, ...: loads of a batch in flight together,
-    // added in increasing t (an absent term adds an exact 0)
-    for (int64_t t0 = s; t0 < nrow; t0 += kSplit * kBatch) {
+    // terms t = s, s + kSplit, ...: the loads of a batch are in flight
+    // together and are added in increasing t (an absent term adds an exact 0)
+    for (int64_t t0 = s; t0 < nterm; t0 += (int64_t)kSplit * kBatch) {
         float v[kBatch][PG];
 #pragma unroll
         for (int q = 0; q < kBatch; ++q) {
             const int64_t t = t0 + (int64_t)q * kSplit;
-            const int64_t lt = tri_index(b, b + t, nb);
+            if (t < nrow) {
+                const int64_t lt = tri_index(b, b + t, nb);
 #pragma unroll
-            for (int c = 0; c < PG; ++c) v[q][c] = (t < nrow) ? rp[(lt * T + kl) * PG + c] : 0.f;
-        }
+                for (int c = 0; c < PG; ++c) v[q][c] = rp[(lt * T + kl) * PG + c];
+            } else {
+                const int64_t tc = t - nrow;
+                const int64_t I = tc / UNITS;
+                const int u = (int)(tc % UNITS);
+                const int64_t lt = tri_index(I, b, nb);
+                // units past n (only in the last tile) were never written
+                const bool ok = (t < nterm) && !(lt == last_lt && I * T + (int64_t)u * kUR >= D.n);
 #pragma unroll
-        for (int q = 0; q < kBatch; ++q)
-#pragma unroll
-            for (int c = 0; c < PG; ++c) acc[c].add(v[q][c]);
-    }
-    // column terms follow the row terms in the same interleaving
-    const int64_t ncol = (b + 1) * UNITS;
-    const int64_t last_lt = tri_count(nb) - 1;
-    for (int64_t t0 = (s - nrow % kSplit + kSplit) % kSplit; t0 < ncol; t0 += kSplit * kBatch) {
-        float v[kBatch][PG];
-#pragma unroll
-        for (int q = 0; q < kBatch; ++q) {
-            const int64_t t = t0 + (int64_t)q * kSplit;
-            const int64_t I = t / UNITS;
-            const int u = (int)(t % UNITS);
-            const int64_t lt = tri_index(I, b, nb);
-            // units past n (only in the last tile) were never written
-            const bool ok = (t < ncol) && !(lt == last_lt && I * T + (int64_t)u * kUR >= D.n);
-#pragma unroll
-            for (int c = 0; c < PG; ++c) v[q][c] = ok ? -cp[((lt * UNITS + u) * T + kl) * PG + c] : 0.f;
+                for (int c = 0; c < PG; ++c) v[q][c] = ok ? -cp[((lt * UNITS + u) * T + kl) * PG + c] : 0.f;
+            }
         }
 #pragma unroll
         for (int q = 0; q < kBatch; ++q)
@@ -441,17 +435,18 @@ __device__ void apply_points(const InstDesc& D, int64_t k0, int mode, float* lds
 // the last tile, hold nothing), in contiguous slices: slice s is a fixed-order
 // sum (each thread takes every kWG-th partial, loads in batches, then a fixed
 // tree), and the stress is the slices added in index order.
-constexpr int kSigSlices = 16;
+constexpr int kSigSlices = 32;
 
 template <int T>
 __device__ __forceinline__ int64_t sigma_count(const InstDesc& D) {
     return tri_count(D.nb) * TileShape<T>::UNITS * kWaves;
 }
-// Slices of the stress sum: about 4096 partials each, at most kSigSlices (one
+// Slices of the stress sum: about kWG * kBatch partials each (one batch of
+// loads per thread), at most kSigSlices (one
 // slice -- written directly, no combining step -- for small instances).
 template <int T>
 __device__ __forceinline__ int sigma_slices(const InstDesc& D) {
-    const int64_t s = sigma_count<T>(D) / 4096;
+    const int64_t s = sigma_count<T>(D) / (kWG * kBatch);
     return (int)(s < 1 ? 1 : (s > kSigSlices ? kSigSlices : s));
 }
 
@@ -754,7 +749,7 @@ hipError_t launch_stress_reduce(const InstDesc* dd, int n_inst, int64_t blocks, 
 // Host mirror of reduce_blocks (must agree with the device functions above).
 int64_t reduce_block_count(int64_t n, int64_t nb, int T) {
     const int64_t cnt = tri_count(nb) * (T / kUR) * kWaves;
-    int64_t ns = cnt / 4096;
+    int64_t ns = cnt / (kWG * kBatch);
     ns = ns < 1 ? 1 : (ns > kSigSlices ? kSigSlices : ns);
     return ns + (n + kWG / kSplit - 1) / (kWG / kSplit);
 }
