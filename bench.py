@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--mode", choices=["auto", "persistent", "batched"], default="auto")
     ap.add_argument("--tile", type=int, default=256)
     ap.add_argument("--sweep-mode", choices=["auto", "persistent", "batched"], default="auto")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="only run a plain device copy of 256 MiB (calibration of memory counters)")
     ap.add_argument("--sweep-tile", type=int, default=0)
     return ap.parse_args()
 
@@ -63,6 +65,16 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.copy_ref:
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_ref_bytes_read": a.numel() * 4, "copy_ref_bytes_written": b.numel() * 4,
+                          "copies": 5}), flush=True)
+        return
 
     from paper_2605_25124_amd import ginimds as gm
     from paper_2605_25124_amd import synth
@@ -95,7 +107,7 @@ def main():
         return gm.Instance(D, Z, nu, gm.LATENT_GINI, 0.0, hist)
 
     if args.mode == "auto":
-        best = gm.gini_autotune([inst(Z0.clone())], 10)
+        best = gm.gini_autotune([inst(Z0.clone())], 30)
     else:
         best = {"flags": gm.SOLVE_PERSISTENT if args.mode == "persistent" else gm.SOLVE_BATCHED,
                 "tile": args.tile, "grid": 0}
@@ -165,7 +177,7 @@ def main():
             return [gm.Instance(Ds[k], Z0s[k].clone(), nus[k]) for k in range(n_inst)]
 
         if args.sweep_mode == "auto":
-            tuned = gm.gini_autotune(insts(), 10)
+            tuned = gm.gini_autotune(insts(), 20)
         else:
             tuned = {"flags": gm.SOLVE_PERSISTENT if args.sweep_mode == "persistent" else gm.SOLVE_BATCHED,
                      "tile": args.sweep_tile or 64, "grid": 0}

@@ -505,7 +505,10 @@ __global__ void k_reset_ctl(gmds::SolveCtl* ctl, uint32_t* ep, int n) {
     if (i < n) ep[i] = 0u;
 }
 
-gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStream_t s) {
+// ev0/ev1 (optional) are recorded right before the first and after the last
+// kernel launch, so that their interval holds only the solve's GPU work.
+gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStream_t s, hipEvent_t ev0 = nullptr,
+                     hipEvent_t ev1 = nullptr) {
     const int n_inst = (int)P.desc.size();
     // one upload: descriptors, then the tile prefix
     const size_t dbytes = (P.desc.size() * sizeof(InstDesc) + 15) & ~size_t(15);
@@ -518,6 +521,11 @@ gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStr
     if (st != GINI_OK) return st;
     const InstDesc* ddp = static_cast<const InstDesc*>(dd);
     const int64_t* dprefix = reinterpret_cast<const int64_t*>(static_cast<unsigned char*>(dd) + dbytes);
+    if (mode == GINI_SOLVE_PERSISTENT) {
+        st = ensure_ctl(c, n_inst);
+        if (st != GINI_OK) return st;
+    }
+    if (ev0) GINI_HIP(c, hipEventRecord(ev0, s));
     if (mode == GINI_SOLVE_PLAIN) {
         for (int k = 0; k < n_inst; ++k) {
             const int64_t nu = P.prefix[k + 1] - P.prefix[k];
@@ -545,8 +553,6 @@ gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStr
                                                    gmds::kModeDescent, it, s));
         }
     } else {
-        st = ensure_ctl(c, n_inst);
-        if (st != GINI_OK) return st;
         hipLaunchKernelGGL(k_reset_ctl, dim3((n_inst + 255) / 256), dim3(256), 0, s, c->ctl, c->epochs, n_inst);
         GINI_HIP(c, hipGetLastError());
         int g = grid;
@@ -557,6 +563,7 @@ gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStr
         GINI_HIP(c, gmds::launch_solve_persistent(ddp, n_inst, dprefix, P.tiles, iters, P.p, P.latent, P.T, g,
                                                   c->ctl, c->epochs, c->spin_limit, s));
     }
+    if (ev1) GINI_HIP(c, hipEventRecord(ev1, s));
     st = slot_done(c, sl, s);
     if (st != GINI_OK) return st;
     GINI_HIP(c, hipStreamSynchronize(s));
@@ -593,11 +600,11 @@ std::string tune_key(const gini_instance* inst, int32_t n_inst) {
 }
 
 gini_status solve_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst, const gini_solve_opts* o,
-                       hipStream_t s);
+                       hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 gini_status autotune_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst, int32_t probe_iters,
                           gini_solve_opts* best, hipStream_t s) {
-    if (probe_iters < 1) probe_iters = 8;
+    if (probe_iters < 1) probe_iters = 20;
     struct ProfPause {
         gini_ctx* c;
         bool was;
@@ -646,9 +653,7 @@ gini_status autotune_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst
                     st = fail(c, GINI_EDEVICE, "autotune: copy failed");
             }
             if (st != GINI_OK) break;
-            (void)hipEventRecord(e0, s);
-            st = solve_impl(c, tmp.data(), n_inst, &cand[ci], s);
-            (void)hipEventRecord(e1, s);
+            st = solve_impl(c, tmp.data(), n_inst, &cand[ci], s, e0, e1);
             (void)hipEventSynchronize(e1);
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, e0, e1);
@@ -672,14 +677,14 @@ gini_status autotune_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst
 }
 
 gini_status solve_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst, const gini_solve_opts* o,
-                       hipStream_t s) {
+                       hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     gini_solve_opts opts = *o;
     if (opts.flags & GINI_SOLVE_AUTOTUNE) {
         const std::string key = tune_key(inst, n_inst);
         auto it = c->tune.find(key);
         gini_solve_opts t{};
         if (it == c->tune.end()) {
-            gini_status st = autotune_impl(c, inst, n_inst, 8, &t, s);
+            gini_status st = autotune_impl(c, inst, n_inst, 20, &t, s);
             if (st != GINI_OK) return st;
         } else {
             t = it->second.opts;
@@ -695,7 +700,7 @@ gini_status solve_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst, c
     gini_status st = make_plan(c, inst, n_inst, T, P, s);
     if (st != GINI_OK) return st;
     if (opts.iters == 0) return GINI_OK;
-    st = run_plan(c, P, opts.iters, solve_mode(opts.flags), opts.grid, s);
+    st = run_plan(c, P, opts.iters, solve_mode(opts.flags), opts.grid, s, ev0, ev1);
     if (st != GINI_OK) return st;
     if (opts.flags & GINI_SOLVE_CHECK_FINITE) {
         std::vector<float> h(opts.iters);

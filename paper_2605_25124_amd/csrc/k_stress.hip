@@ -18,8 +18,9 @@
 // Reduction.  A unit writes one partial per row (complete for that tile), one
 // partial per column and its stress.  A second launch sums, for every point, the
 // row partials of its tile row and the column partials of its tile column in a
-// fixed order (sixteen interleaved Neumaier sums combined in index order), and
-// either writes the gradient or takes the descent step.  No floating-point
+// fixed order (sixteen interleaved Neumaier sums, one wave each over 64
+// consecutive points, combined in index order), and either writes the
+// gradient or takes the descent step.  No floating-point
 // atomics anywhere: results are bitwise reproducible and independent of
 // scheduling and of how many instances share a launch.
 #include "common.hpp"
@@ -332,10 +333,19 @@ __device__ __forceinline__ void stress_unit(const InstDesc& D, int64_t lu, float
     else unit_body<P, LAT, T, GRAD, true>(D, lt, sub, I, J, lds);
 }
 
-// Gradient of point k: row partials of its tile row, column partials of its
-// tile column (every unit of each tile), as kSplit interleaved Neumaier sums
-// -- this thread takes terms s, s + kSplit, ... -- combined later in index
-// order.  Row and column terms share one sequence: t < nrow are row terms.
+// ---------------------------------------------------------------- reduction
+// Every sum below has a fixed shape that does not depend on how many threads
+// execute it, so the reduction launch (kRedWG threads) and the persistent
+// solver (kWG threads) produce bitwise identical results.
+constexpr int kRedWG = 1024;             // threads of a reduction block
+constexpr int kNPT = 64;                 // points per reduction group (one per lane)
+constexpr int kVT = 1024;                // virtual threads of a stress slice
+
+// Partial gradient of point k: terms t = s, s + kSplit, ... of the sequence
+// "row partials of its tile row (tiles (b, b..nb-1)), then column partials of
+// its tile column (every unit of tiles (0..b, b))", summed (Neumaier) in
+// increasing t.  The loads of a batch are in flight together; an absent term
+// adds an exact 0.
 template <int P, int LAT, int T>
 __device__ __forceinline__ void point_partial(const InstDesc& D, int64_t k, int s, Comp (&acc)[PG_<P, LAT>::value]) {
     constexpr int PG = PG_<P, LAT>::value;
@@ -343,13 +353,11 @@ __device__ __forceinline__ void point_partial(const InstDesc& D, int64_t k, int 
     const int64_t b = k / T;
     const int64_t kl = k % T;
     const int64_t nb = D.nb;
-    const int64_t nrow = nb - b;                       // row partials: tiles (b, b..nb-1)
-    const int64_t nterm = nrow + (b + 1) * UNITS;      // then column partials: units of tiles (0..b, b)
+    const int64_t nrow = nb - b;
+    const int64_t nterm = nrow + (b + 1) * UNITS;
     const int64_t last_lt = tri_count(nb) - 1;
     gfl* rp = gp(D.rowpart);
     gfl* cp = gp(D.colpart);
-    // terms t = s, s + kSplit, ...: the loads of a batch are in flight
-    // together and are added in increasing t (an absent term adds an exact 0)
     for (int64_t t0 = s; t0 < nterm; t0 += (int64_t)kSplit * kBatch) {
         float v[kBatch][PG];
 #pragma unroll
@@ -377,37 +385,40 @@ __device__ __forceinline__ void point_partial(const InstDesc& D, int64_t k, int 
     }
 }
 
-// Combine the kSplit partial sums of each point (held in LDS) and apply the
-// result.  Threads are laid out as [kSplit][kWG / kSplit] points.
-template <int P, int LAT, int T>
-__device__ void apply_points(const InstDesc& D, int64_t k0, int mode, float* lds) {
+// Gradient of the kNPT points k0 .. k0+kNPT-1: the kSplit partial sums of each
+// point (one wave per partial sum: 64 consecutive points, coalesced loads)
+// are added in index order, scaled by the common factor and applied.  NT is
+// the number of threads executing the call.  LDS: 2 * kSplit * kNPT * PG floats.
+template <int P, int LAT, int T, int NT>
+__device__ void reduce_group(const InstDesc& D, int64_t k0, int mode, float* lds) {
     constexpr int PG = PG_<P, LAT>::value;
-    constexpr int NPT = kWG / kSplit;
     const int tid = threadIdx.x;
-    const int s = tid / NPT;
-    const int pl = tid % NPT;
-    const int64_t k = k0 + pl;
-    Comp acc[PG];
-    if (k < D.n) point_partial<P, LAT, T>(D, k, s, acc);
-    __syncthreads();
+    for (int item = tid; item < kSplit * kNPT; item += NT) {
+        const int sp = item / kNPT;
+        const int pl = item % kNPT;
+        const int64_t k = k0 + pl;
+        Comp acc[PG];
+        if (k < D.n) point_partial<P, LAT, T>(D, k, sp, acc);
 #pragma unroll
-    for (int c = 0; c < PG; ++c) {
-        lds[(c * kSplit + s) * NPT * 2 + 2 * pl] = acc[c].hi;
-        lds[(c * kSplit + s) * NPT * 2 + 2 * pl + 1] = acc[c].lo;
+        for (int c = 0; c < PG; ++c) {
+            lds[((c * kSplit + sp) * kNPT + pl) * 2] = acc[c].hi;
+            lds[((c * kSplit + sp) * kNPT + pl) * 2 + 1] = acc[c].lo;
+        }
     }
     __syncthreads();
-    if (s == 0 && k < D.n) {
-        float G[P];
+    if (tid < kNPT && k0 + tid < D.n) {
+        const int pl = tid;
+        const int64_t k = k0 + pl;
         Comp tot[PG];
 #pragma unroll
         for (int c = 0; c < PG; ++c)
-#pragma unroll
             for (int q = 0; q < kSplit; ++q) {
                 Comp x;
-                x.hi = lds[(c * kSplit + q) * NPT * 2 + 2 * pl];
-                x.lo = lds[(c * kSplit + q) * NPT * 2 + 2 * pl + 1];
+                x.hi = lds[((c * kSplit + q) * kNPT + pl) * 2];
+                x.lo = lds[((c * kSplit + q) * kNPT + pl) * 2 + 1];
                 tot[c].add(x);
             }
+        float G[P];
         if constexpr (P == 2 && LAT == 0) {
             const float v = 2.f * D.c2 * tot[0].value();
             G[0] = -v;
@@ -432,25 +443,25 @@ __device__ void apply_points(const InstDesc& D, int64_t k0, int mode, float* lds
 }
 
 // Stress of instance D from the per-wave unit partials (units past n, only in
-// the last tile, hold nothing), in contiguous slices: slice s is a fixed-order
-// sum (each thread takes every kWG-th partial, loads in batches, then a fixed
-// tree), and the stress is the slices added in index order.
+// the last tile, hold nothing), in contiguous slices.  A slice is a fixed
+// shape sum: virtual thread v < kVT adds partials a+v, a+v+kVT, ... in order,
+// then a fixed binary tree over the kVT values; slices are added in order.
 constexpr int kSigSlices = 32;
 
 template <int T>
 __device__ __forceinline__ int64_t sigma_count(const InstDesc& D) {
     return tri_count(D.nb) * TileShape<T>::UNITS * kWaves;
 }
-// Slices of the stress sum: about kWG * kBatch partials each (one batch of
-// loads per thread), at most kSigSlices (one
-// slice -- written directly, no combining step -- for small instances).
+// About kVT * kBatch partials per slice, at most kSigSlices (one slice --
+// written directly, no combining step -- for small instances).
 template <int T>
 __device__ __forceinline__ int sigma_slices(const InstDesc& D) {
-    const int64_t s = sigma_count<T>(D) / (kWG * kBatch);
+    const int64_t s = sigma_count<T>(D) / (kVT * kBatch);
     return (int)(s < 1 ? 1 : (s > kSigSlices ? kSigSlices : s));
 }
 
-template <int T>
+// LDS: 2 * kVT floats.  All NT threads return the slice sum.
+template <int T, int NT>
 __device__ Comp sigma_slice(const InstDesc& D, int slice, float* lds) {
     constexpr int UNITS = TileShape<T>::UNITS;
     const int64_t nt = tri_count(D.nb);
@@ -459,35 +470,58 @@ __device__ Comp sigma_slice(const InstDesc& D, int slice, float* lds) {
     const int64_t a = cnt * slice / ns;
     const int64_t e = cnt * (slice + 1) / ns;
     gfl* sp = gp(D.sigpart);
-    Comp acc;
-    for (int64_t t0 = a + threadIdx.x; t0 < e; t0 += (int64_t)kWG * kBatch) {
-        float hv[kBatch], lv[kBatch];
+    for (int vt = threadIdx.x; vt < kVT; vt += NT) {
+        Comp acc;
+        for (int64_t t0 = a + vt; t0 < e; t0 += (int64_t)kVT * kBatch) {
+            float hv[kBatch], lv[kBatch];
 #pragma unroll
-        for (int q = 0; q < kBatch; ++q) {
-            const int64_t t = t0 + (int64_t)q * kWG;
-            const int64_t lu = t / kWaves;
-            const int u = (int)(lu % UNITS);
-            const bool ok = (t < e) && !(lu / UNITS == nt - 1 && (D.nb - 1) * T + (int64_t)u * kUR >= D.n);
-            hv[q] = ok ? sp[2 * t] : 0.f;
-            lv[q] = ok ? sp[2 * t + 1] : 0.f;
-        }
+            for (int q = 0; q < kBatch; ++q) {
+                const int64_t t = t0 + (int64_t)q * kVT;
+                const int64_t lu = t / kWaves;
+                const int u = (int)(lu % UNITS);
+                const bool ok = (t < e) && !(lu / UNITS == nt - 1 && (D.nb - 1) * T + (int64_t)u * kUR >= D.n);
+                hv[q] = ok ? sp[2 * t] : 0.f;
+                lv[q] = ok ? sp[2 * t + 1] : 0.f;
+            }
 #pragma unroll
-        for (int q = 0; q < kBatch; ++q) {
-            Comp x;
-            x.hi = hv[q];
-            x.lo = lv[q];
-            acc.add(x);
+            for (int q = 0; q < kBatch; ++q) {
+                Comp x;
+                x.hi = hv[q];
+                x.lo = lv[q];
+                acc.add(x);
+            }
         }
+        lds[vt] = acc.hi;
+        lds[kVT + vt] = acc.lo;
     }
-    return wg_sum(acc, lds);
+    __syncthreads();
+    for (int st = kVT / 2; st > 0; st >>= 1) {
+        for (int x = threadIdx.x; x < st; x += NT) {
+            Comp u;
+            u.hi = lds[x];
+            u.lo = lds[kVT + x];
+            Comp w;
+            w.hi = lds[x + st];
+            w.lo = lds[kVT + x + st];
+            u.add(w);
+            lds[x] = u.hi;
+            lds[kVT + x] = u.lo;
+        }
+        __syncthreads();
+    }
+    Comp r;
+    r.hi = lds[0];
+    r.lo = lds[kVT];
+    __syncthreads();
+    return r;
 }
 
-template <int T>
+template <int T, int NT>
 __device__ Comp instance_sigma(const InstDesc& D, float* lds) {
     const int ns = sigma_slices<T>(D);
-    if (ns == 1) return sigma_slice<T>(D, 0, lds);
+    if (ns == 1) return sigma_slice<T, NT>(D, 0, lds);
     Comp tot;
-    for (int sl = 0; sl < ns; ++sl) tot.add(sigma_slice<T>(D, sl, lds));
+    for (int sl = 0; sl < ns; ++sl) tot.add(sigma_slice<T, NT>(D, sl, lds));
     return tot;
 }
 
@@ -523,22 +557,26 @@ __global__ __launch_bounds__(kWG) void k_stress_units(const InstDesc* __restrict
 }
 
 // Number of reduction blocks of an instance: its stress slices, then one
-// block per kWG / kSplit points.
+// block per kNPT points.
 template <int T>
 __device__ __forceinline__ int64_t reduce_blocks(const InstDesc& D) {
-    return sigma_slices<T>(D) + (D.n + kWG / kSplit - 1) / (kWG / kSplit);
+    return sigma_slices<T>(D) + (D.n + kNPT - 1) / kNPT;
+}
+
+template <int PG>
+constexpr int reduce_lds_floats() {
+    return 2 * kSplit * kNPT * PG > 2 * kVT ? 2 * kSplit * kNPT * PG : 2 * kVT;
 }
 
 // Reduction launch over the concatenated blocks of all instances (block
 // offsets in red_off).  The first blocks of an instance sum one slice of its
 // stress each (with several slices, the last to finish adds them in order);
-// the following blocks take kWG / kSplit points each.
+// the following blocks take kNPT points each.
 template <int P, int LAT, int T>
-__global__ __launch_bounds__(kWG) void k_stress_reduce(const InstDesc* __restrict__ dd, int n_inst, int64_t q_base,
-                                                       int mode, int it) {
+__global__ __launch_bounds__(kRedWG) void k_stress_reduce(const InstDesc* __restrict__ dd, int n_inst,
+                                                          int64_t q_base, int mode, int it) {
     constexpr int PG = PG_<P, LAT>::value;
-    constexpr int NPT = kWG / kSplit;
-    __shared__ float lds[2 * kSplit * NPT * PG > 2 * kWG ? 2 * kSplit * NPT * PG : 2 * kWG];
+    __shared__ float lds[reduce_lds_floats<PG>()];
     __shared__ int last;
     const int64_t q = (int64_t)blockIdx.x + q_base;
     int lo = 0, hi = n_inst - 1;
@@ -551,7 +589,7 @@ __global__ __launch_bounds__(kWG) void k_stress_reduce(const InstDesc* __restric
     const int64_t b = q - D.red_off;
     const int ns = sigma_slices<T>(D);
     if (b < ns) {
-        const Comp part = sigma_slice<T>(D, (int)b, lds);
+        const Comp part = sigma_slice<T, kRedWG>(D, (int)b, lds);
         if (threadIdx.x == 0) {
             if (ns == 1) {
                 write_sigma(D, mode, it, part);
@@ -579,7 +617,7 @@ __global__ __launch_bounds__(kWG) void k_stress_reduce(const InstDesc* __restric
         return;
     }
     if (mode == kModeSigma) return;
-    apply_points<P, LAT, T>(D, (b - ns) * NPT, mode, lds);
+    reduce_group<P, LAT, T, kRedWG>(D, (b - ns) * kNPT, mode, lds);
 }
 
 __global__ void k_fill_u32(uint32_t* p, int64_t count, uint32_t v) {
@@ -606,7 +644,7 @@ __global__ __launch_bounds__(kWG) void k_solve_persistent(const InstDesc* __rest
     constexpr int PG = PG_<P, LAT>::value;
     constexpr int UNITS = TileShape<T>::UNITS;
     constexpr int NL1 = unit_lds_floats<P, T>();
-    constexpr int NL2 = 2 * kSplit * (kWG / kSplit) * PG;
+    constexpr int NL2 = reduce_lds_floats<PG>();
     __shared__ float lds[NL1 > NL2 ? NL1 : NL2];
     __shared__ int64_t sh_q;
     __shared__ int sh_flag;
@@ -670,9 +708,9 @@ __global__ __launch_bounds__(kWG) void k_solve_persistent(const InstDesc* __rest
         __syncthreads();
         if (sh_flag) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            const Comp s = instance_sigma<T>(D, lds);
+            const Comp s = instance_sigma<T, kWG>(D, lds);
             write_sigma(D, kModeDescent, it, s);
-            for (int64_t k0 = 0; k0 < D.n; k0 += kWG / kSplit) apply_points<P, LAT, T>(D, k0, kModeDescent, lds);
+            for (int64_t k0 = 0; k0 < D.n; k0 += kNPT) reduce_group<P, LAT, T, kWG>(D, k0, kModeDescent, lds);
             __threadfence();
             __syncthreads();
             if (tid == 0) {
@@ -701,7 +739,7 @@ template <int P, int LAT, int T>
 static hipError_t reduce_impl(const InstDesc* dd, int n_inst, int64_t blocks, int64_t qb, int mode, int it,
                               hipStream_t s) {
     if (blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_stress_reduce<P, LAT, T>), dim3((unsigned)blocks), dim3(kWG), 0, s, dd, n_inst, qb, mode,
+    hipLaunchKernelGGL((k_stress_reduce<P, LAT, T>), dim3((unsigned)blocks), dim3(kRedWG), 0, s, dd, n_inst, qb, mode,
                        it);
     return hipGetLastError();
 }
@@ -749,9 +787,9 @@ hipError_t launch_stress_reduce(const InstDesc* dd, int n_inst, int64_t blocks, 
 // Host mirror of reduce_blocks (must agree with the device functions above).
 int64_t reduce_block_count(int64_t n, int64_t nb, int T) {
     const int64_t cnt = tri_count(nb) * (T / kUR) * kWaves;
-    int64_t ns = cnt / (kWG * kBatch);
+    int64_t ns = cnt / (kVT * kBatch);
     ns = ns < 1 ? 1 : (ns > kSigSlices ? kSigSlices : ns);
-    return ns + (n + kWG / kSplit - 1) / (kWG / kSplit);
+    return ns + (n + kNPT - 1) / kNPT;
 }
 
 int units_per_tile(int T) { return T / kUR; }
