@@ -4,12 +4,12 @@
  * The library computes, on one GPU, the data-parallel hot path of Gini
  * multidimensional scaling (arXiv 2605.25124):
  *   - the doubled midranks of the coordinates of a vector (Definition 1 with
- *     the tie rule of Section 2.1),
+ *     the tie rule of Section III-A),
  *   - the matrix of generalised Gini pseudo-distances between all pairs of
- *     rows of a data matrix (Section 2.2; the "compute Gini pseudo-distances"
- *     step of Algorithm 1),
+ *     rows of a data matrix (Section III-B; the distance-matrix step of
+ *     Algorithm 1),
  *   - the raw stress of a latent configuration against that matrix and its
- *     gradient (the SMACOF loss of Section 3.2 with unit weights), with the
+ *     gradient (the SMACOF loss of Section IV-B with unit weights), with the
  *     latent coordinates re-ranked at every evaluation,
  *   - fixed-step gradient-descent fits of many such problems, including a
  *     sweep over nu (Algorithm 1), in one persistent launch.
@@ -55,8 +55,8 @@ typedef enum {
 } gini_status;
 
 /* Distance used between latent points.  GINI: the generalised Gini
- * pseudo-distance of Section 2.2 over the p latent coordinates (the latent
- * space is a Gini metric space, Section 3.2).  EUCLID: the Euclidean norm
+ * pseudo-distance of Section III-B over the p latent coordinates (the latent
+ * space is a Gini metric space, Section IV-B).  EUCLID: the Euclidean norm
  * used by Algorithm 1 to evaluate the Kruskal stress. */
 typedef enum { GINI_LATENT_GINI = 0, GINI_LATENT_EUCLID = 1 } gini_latent;
 
@@ -79,7 +79,7 @@ int gini_version(void);
 /*
  * gini_weight_table -- host-side table used by every kernel: the weight a
  * coordinate of doubled midrank t receives in the symmetrised generalised
- * Gini pseudo-distance of d-vectors (Section 2.2, with the survival function
+ * Gini pseudo-distance of d-vectors (Section III-B, with the survival function
  * of a coordinate taken as 1 - R/d):
  *     W[t-2] = ((t-2)/(2d))^(nu-1) - ((2d-t)/(2d))^(nu-1),  t = 2 .. 2d,
  * computed in FP64 and rounded once to FP32; exactly antisymmetric,
@@ -90,7 +90,7 @@ gini_status gini_weight_table(int32_t d, double nu, float* W);
 
 /*
  * gini_rank -- doubled midranks of every row of V (Definition 1; ties share
- * the mean of the ranks they occupy, the rule of Section 2.1, so that the zero
+ * the mean of the ranks they occupy, the rule of Section III-A, so that the zero
  * vector has R = (d+1)/2 everywhere):
  *     twoR[r*ldr + c] = 2*#{c' : V[r,c'] < V[r,c]} + #{c' : V[r,c'] == V[r,c]} + 1
  * V: rows x d FP32, leading dimension ldv >= d.  twoR: rows x d int32,
@@ -102,7 +102,7 @@ gini_status gini_rank(gini_ctx* ctx, const float* V, int64_t rows, int32_t d, in
 
 /*
  * gini_dissim -- generalised Gini pseudo-distance between every pair of rows
- * of X (Section 2.2, symmetrised form), for each nu in a list, from one
+ * of X (Section III-B, symmetrised form), for each nu in a list, from one
  * ranking of each pair's difference vector:
  *     Delta_k[i, j] = (m/2) * sum_c z_c * W_{m,nu_k}[t_c],   z = fl32(X_i - X_j),
  *     t = doubled midranks of z,
@@ -123,8 +123,21 @@ gini_status gini_dissim(gini_ctx* ctx, const float* X, int64_t n, int32_t m, int
                         int64_t stride_nu, gini_stream_t stream);
 
 /*
+ * gini_sumsq -- the normaliser of the Kruskal stress (the stress formula that
+ * Algorithm 1 evaluates, Section IV-B):
+ *     out[2k] + out[2k+1] = sum_{i<j} Delta_k[i, j]^2,   k = 0 .. n_mat-1
+ * Delta: n_mat matrices n x n FP32 (ldd >= n), matrix k at Delta + k*stride
+ * (stride >= n*ldd when n_mat > 1); only the strict upper triangle is read.
+ * out: device float[2*n_mat], (hi, lo) per matrix; n = 1 gives 0.  Each
+ * square is split exactly into two FP32 terms and summed with compensation
+ * in a fixed order: deterministic.  n >= 1, 1 <= n_mat <= 65535.
+ */
+gini_status gini_sumsq(gini_ctx* ctx, const float* Delta, int64_t n, int64_t ldd, int32_t n_mat,
+                       int64_t stride, float* out, gini_stream_t stream);
+
+/*
  * gini_stress_fwd -- raw stress of the configuration Z against Delta (the
- * SMACOF loss of Section 3.2 with unit weights, pairs i < j):
+ * SMACOF loss of Section IV-B with unit weights, pairs i < j):
  *     sigma = sum_{i<j} (delta(Z_i - Z_j) - Delta[i,j])^2
  * where delta is the latent distance (gini_latent): for GINI the Gini
  * pseudo-distance of the p latent coordinates at the given nu, re-ranked for
@@ -167,6 +180,10 @@ typedef struct {
     gini_latent latent;
     float eta;             /* step; <= 0 selects 1 / (2 n c) (see below)       */
     float* sigma_hist;     /* iters floats: sigma(Z_t) before step t; or NULL  */
+    const float* delta_sumsq; /* (hi, lo) from gini_sumsq of this Delta, or
+                                 NULL; needed only by ks_hist                 */
+    float* ks_hist;        /* iters floats: Kruskal stress
+                              sqrt(sigma(Z_t) / sum_{i<j} Delta_ij^2); or NULL */
 } gini_instance;
 
 enum {
@@ -186,14 +203,17 @@ typedef struct {
 } gini_solve_opts;
 
 /*
- * gini_mds_solve -- "Run MDS" of Algorithm 1: for every instance, iters
+ * gini_mds_solve -- the MDS fit of Algorithm 1: for every instance, iters
  * fixed steps of gradient descent on the raw stress,
  *     sigma_hist[t] = sigma(Z_t),   Z_{t+1} = Z_t - eta * grad sigma(Z_t),
  * with default eta = 1 / (2 n c), c = |d delta / d u|^2 at a tie-free u
  * (c = 1 for EUCLID, where the step is the Guttman transform of SMACOF plus
  * a translation; c = 2 * 4^(1-nu) for GINI at p = 2).
  * inst: HOST array of n_inst descriptors (1 <= n_inst <= 65536).  Instances
- * must not share Z or sigma_hist.  The three modes give bitwise identical
+ * must not share Z, sigma_hist or ks_hist; an instance with ks_hist needs
+ * delta_sumsq, and ks_hist[t] = sqrt(sigma_hist[t] / (delta_sumsq[0] +
+ * delta_sumsq[1])) is formed in FP64 from the compensated sigma (0 when the
+ * normaliser is 0).  The three modes give bitwise identical
  * results for the same tile size.  Synchronises `stream` before returning
  * (to report device-side failures); a persistent launch that stops making
  * progress aborts and returns GINI_EDEVICE.

@@ -16,18 +16,19 @@
  * Readings taken where the paper is silent or garbled (each one is also
  * listed in the design notes):
  *   R1  ties get midranks, R(v_c) = #{v < v_c} + (#{v == v_c} + 1) / 2
- *       (the "midpoints" of Section 2.1; the printed tie formula is garbled).
+ *       (tied values share the midpoint of their ranks, as Section III-A
+ *       intends; the printed tie formula is garbled).
  *       Ranks are returned doubled, t = 2R, so that they are integers.
- *   R2  inside the generalised distance of Section 2.2 the survival function
+ *   R2  inside the generalised distance of Section III-B the survival function
  *       of a coordinate of the compared difference vector is the empirical
  *       one over its d coordinates, Fbar(z_c) = 1 - R(z_c)/d, and
  *       Fbar(0) = 1 - R(0)/d with R(0) = (d+1)/2 (as for the Gini norm).
- *   R3  the "d" multiplying the sum is the length of the compared vectors.
+ *   R3  the factor d multiplying the sum is the length of the compared vectors.
  *   R4  the latent distance is selectable: the Gini pseudo-distance itself
- *       (Section 3.2 fits a Gini metric space) or the Euclidean norm
+ *       (Section IV-B fits a Gini metric space) or the Euclidean norm
  *       (Algorithm 1 evaluates the fit with Euclidean latent distances).
  *   R5  the minimised loss is the raw stress sum_{i<j} (delta_ij - Delta_ij)^2
- *       (the SMACOF loss of Section 3.2 with unit weights).
+ *       (the SMACOF loss of Section IV-B with unit weights).
  *   R6  ranks are held fixed when differentiating (the distance is piecewise
  *       linear in the data), which gives the gradient almost everywhere.
  *   R7  the fixed step is eta = eta_s / (2 n c) with c = |d delta / d u|^2 for
@@ -127,7 +128,7 @@ static void orc_ws_free(orc_gini_ws* w) {
     free(w->g); free(w->t_pos); free(w->t_neg); free(w->zneg);
 }
 
-/* Section 2.2, asymmetric generalised Gini pseudo-distance written for the
+/* Section III-B, asymmetric generalised Gini pseudo-distance written for the
  * difference z = x - y:  -d * sum_j z_j (Fbar(z_j)^{nu-1} - Fbar(0)^{nu-1}). */
 static double orc_asym(const double* z, const int32_t* t, const orc_gini_ws* w) {
     double s = 0.0;
@@ -135,7 +136,7 @@ static double orc_asym(const double* z, const int32_t* t, const orc_gini_ws* w) 
     return -(double)w->d * s;
 }
 
-/* Section 2.2, symmetrised distance: half D(x,y) plus half D(y,x).  D(y,x)
+/* Section III-B, symmetrised distance: half D(x,y) plus half D(y,x).  D(y,x)
  * ranks y - x = -z afresh (no mirror identity is assumed).  Optional grad
  * returns d/dz_c with both rank vectors held fixed (R6):
  *   (d/2) (Fbar(-z_c)^{nu-1} - Fbar(z_c)^{nu-1}). */
@@ -192,7 +193,7 @@ static double orc_diff(double a, double b, int mode) {
     return a - b;
 }
 
-/* Algorithm 1, "compute Gini pseudo-distances": the full symmetric n x n
+/* Algorithm 1, distance-matrix step: the full symmetric n x n
  * matrix for each nu in the list (zero diagonal, pairs i<j computed, mirrored). */
 void orc_dissim(const double* X, int64_t n, int m, int64_t ldx, int mode,
                 const double* nus, int n_nu, double* Delta, int64_t ldd, int64_t stride_nu) {
@@ -247,6 +248,15 @@ static double orc_latent(const double* u, int p, int latent, orc_gini_ws* w, dou
 
 /* Raw stress (R5) sigma = sum_{i<j} (delta(Z_i - Z_j) - Delta_ij)^2 and its
  * gradient G (n x p, may be NULL): G_i += 2 r a, G_j -= 2 r a. */
+/* Section IV-B, Kruskal stress KS = sqrt(sigma / sum_{i<j} Delta_ij^2): its
+ * normaliser, summed over the pairs i < j. */
+double orc_delta_sumsq(const double* Delta, int64_t n, int64_t ldd) {
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = i + 1; j < n; ++j) s += Delta[i * ldd + j] * Delta[i * ldd + j];
+    return s;
+}
+
 double orc_stress(const double* Delta, int64_t n, int64_t ldd, const double* Z, int p, int64_t ldz,
                   double nu, int latent, int mode, double* G, int64_t ldg) {
     orc_gini_ws w;
@@ -319,7 +329,7 @@ double orc_step_size(int64_t n, int p, double nu, int latent) {
     return 1.0 / (2.0 * (double)n * c);
 }
 
-/* "Run MDS" of Algorithm 1 read as R5-R7: iters fixed steps Z <- Z - eta G,
+/* The MDS fit of Algorithm 1 read as R5-R7: iters fixed steps Z <- Z - eta G,
  * recording sigma(Z_t) before each step.  eta <= 0 selects the default. */
 void orc_solve(const double* Delta, int64_t n, int64_t ldd, double* Z, int p, int64_t ldz, double nu,
                int latent, int mode, int iters, double eta, double* sigma_hist) {

@@ -62,6 +62,8 @@ def lib():
         L.orc_dissim_pairs.argtypes = [P, i32, i64, i32, P, P, i64, P, i32, P]
         L.orc_stress.argtypes = [P, i64, i64, P, i32, i64, f64, i32, i32, P, i64]
         L.orc_stress.restype = f64
+        L.orc_delta_sumsq.argtypes = [P, i64, i64]
+        L.orc_delta_sumsq.restype = f64
         L.orc_grad_rows.argtypes = [P, i64, P, i64, i64, P, i32, i64, f64, i32, i32, P, i64]
         L.orc_grad_rows.restype = f64
         L.orc_step_size.argtypes = [i64, i32, f64, i32]
@@ -146,6 +148,19 @@ def stress(Delta, Z, nu: float, latent: int = LATENT_GINI, mode: int = MATCH32, 
     s = lib().orc_stress(_ptr(D), n, D.shape[1], _ptr(Z), p, p, float(nu), latent, mode,
                          _ptr(G) if grad else None, p)
     return float(s), G
+
+
+def delta_sumsq(Delta) -> float:
+    """sum_{i<j} Delta_ij^2, the Kruskal-stress normaliser."""
+    D = _f64(Delta)
+    return float(lib().orc_delta_sumsq(_ptr(D), D.shape[0], D.shape[1]))
+
+
+def kruskal(Delta, Z, nu: float, latent: int = LATENT_GINI, mode: int = MATCH32) -> float:
+    """Kruskal stress sqrt(sigma / sum_{i<j} Delta_ij^2) of Z against Delta."""
+    s, _ = stress(Delta, Z, nu, latent, mode, grad=False)
+    den = delta_sumsq(Delta)
+    return float(np.sqrt(s / den)) if den > 0 else 0.0
 
 
 def grad_rows(Drows, rows, Z, nu: float, latent: int = LATENT_GINI, mode: int = MATCH32):

@@ -432,6 +432,8 @@ gini_status validate_instances(gini_ctx* c, const gini_instance* inst, int32_t n
         if (I.ldz < I.p) return fail(c, GINI_EINVAL, "instance %d: ldz < p", k);
         if (I.reserved0 != 0) return fail(c, GINI_EINVAL, "instance %d: reserved0 must be 0", k);
         if (!std::isfinite(I.eta)) return fail(c, GINI_EINVAL, "instance %d: eta not finite", k);
+        if (I.ks_hist && !I.delta_sumsq)
+            return fail(c, GINI_EINVAL, "instance %d: ks_hist needs delta_sumsq", k);
         gini_status st = check_latent(c, I.p, I.nu, I.latent);
         if (st != GINI_OK) return fail(c, st, "instance %d: %s", k, c->err.c_str());
         if (I.p != inst[0].p || I.latent != inst[0].latent)
@@ -442,6 +444,8 @@ gini_status validate_instances(gini_ctx* c, const gini_instance* inst, int32_t n
             if (inst[k].Z == inst[l].Z) return fail(c, GINI_EINVAL, "instances %d and %d share Z", k, l);
             if (inst[k].sigma_hist && inst[k].sigma_hist == inst[l].sigma_hist)
                 return fail(c, GINI_EINVAL, "instances %d and %d share sigma_hist", k, l);
+            if (inst[k].ks_hist && inst[k].ks_hist == inst[l].ks_hist)
+                return fail(c, GINI_EINVAL, "instances %d and %d share ks_hist", k, l);
         }
     return GINI_OK;
 }
@@ -465,6 +469,8 @@ gini_status make_plan(gini_ctx* c, const gini_instance* inst, int32_t n_inst, in
         D.Delta = I.Delta;
         D.Z = I.Z;
         D.sigma_hist = I.sigma_hist;
+        D.dsumsq = I.delta_sumsq;
+        D.ks_hist = I.ks_hist;
         D.n = I.n;
         D.ldd = I.ldd;
         D.ldz = I.ldz;
@@ -623,6 +629,7 @@ gini_status autotune_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst
         }
         tmp[k].Z = zcopy[k];
         tmp[k].sigma_hist = nullptr;
+        tmp[k].ks_hist = nullptr;
     }
     std::vector<gini_solve_opts> cand;
     int64_t maxn = 0;
@@ -848,6 +855,25 @@ gini_status gini_dissim(gini_ctx* c, const float* X, int64_t n, int32_t m, int64
     a.half_m = 0.5f * (float)m;
     ProfScope ps(c, kProfDissim, s);
     GINI_HIP(c, gmds::launch_dissim(a, s));
+    return GINI_OK;
+}
+
+gini_status gini_sumsq(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, int32_t n_mat, int64_t stride,
+                       float* out, gini_stream_t stream) {
+    if (!c) return GINI_EINVAL;
+    c->err.clear();
+    if (!Delta || !out) return fail(c, GINI_EINVAL, "Delta and out must be non-null");
+    if (n < 1) return fail(c, GINI_EINVAL, "n = %lld < 1", (long long)n);
+    if (ldd < n) return fail(c, GINI_EINVAL, "ldd = %lld < n = %lld", (long long)ldd, (long long)n);
+    if (n_mat < 1 || n_mat > 65535) return fail(c, GINI_EINVAL, "n_mat = %d outside 1..65535", n_mat);
+    if (n_mat > 1 && stride < n * ldd) return fail(c, GINI_EINVAL, "stride = %lld < n*ldd", (long long)stride);
+    if (n > (int64_t)1 << 31) return fail(c, GINI_EUNSUPPORTED, "n too large");
+    gini_status st = ensure_ready(c);
+    if (st != GINI_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    st = ensure_scratch(c, (size_t)2 * n_mat * std::max<int64_t>(1, gmds::sumsq_blocks(n)) * sizeof(float));
+    if (st != GINI_OK) return st;
+    GINI_HIP(c, gmds::launch_sumsq(Delta, n, ldd, n_mat, n_mat > 1 ? stride : 0, c->scratch, out, s));
     return GINI_OK;
 }
 

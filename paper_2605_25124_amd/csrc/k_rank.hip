@@ -1,5 +1,5 @@
 // k_rank.hip -- doubled midranks of the coordinates of each row (Definition 1
-// with the tie rule of Section 2.1):
+// with the tie rule of Section III-A):
 //     t_c = 2 * #{c' : v_c' < v_c} + #{c' : v_c' == v_c} + 1.
 // Each thread counts for its own coordinates against the whole row, staged in
 // LDS so that the threads of a row read the same word at the same time

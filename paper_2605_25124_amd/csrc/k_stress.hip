@@ -529,6 +529,11 @@ __device__ __forceinline__ void write_sigma(const InstDesc& D, int mode, int it,
     if (threadIdx.x != 0) return;
     if (mode == kModeDescent) {
         if (D.sigma_hist) D.sigma_hist[it] = s.hi + s.lo;
+        if (D.ks_hist) {
+            const double den = (double)D.dsumsq[0] + (double)D.dsumsq[1];
+            const double num = (double)s.hi + (double)s.lo;
+            D.ks_hist[it] = den > 0.0 ? (float)sqrt(num / den) : 0.f;
+        }
     } else if (D.out_sigma) {
         D.out_sigma[0] = s.hi;
         D.out_sigma[1] = s.lo;

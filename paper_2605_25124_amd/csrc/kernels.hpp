@@ -19,6 +19,8 @@ struct InstDesc {
     float* gradZ;          // n x p gradient output (single evaluation), or nullptr
     const float* grad_out; // device scalar multiplying gradZ, or nullptr
     float* out_sigma;      // device (hi, lo), or nullptr
+    const float* dsumsq;   // device (hi, lo) of sum_{i<j} Delta_ij^2 (Kruskal normaliser), or nullptr
+    float* ks_hist;        // per-iteration Kruskal stress (descent only), or nullptr
     float* rowpart;        // scratch: [ntiles][T][pg] row partial gradients (one per row and tile)
     float* colpart;        // scratch: [ntiles][units][T][pg] column partial gradients (one per unit)
     float* sigpart;        // scratch: [ntiles][units][kStressWaves][2] partial stress (hi, lo) per wave
@@ -86,6 +88,11 @@ hipError_t launch_solve_persistent(const InstDesc* dd, int n_inst, const int64_t
 int persistent_max_blocks_per_cu(int p, int latent, int T);
 // Set `count` words to `value` (counters, epochs).
 hipError_t launch_fill_u32(uint32_t* ptr, int64_t count, uint32_t value, hipStream_t s);
+// sum_{i<j} Delta_ij^2 of n_mat stacked matrices into out[2k], out[2k+1]
+// (hi, lo); `part` holds 2 * n_mat * sumsq_blocks(n) floats of scratch.
+int64_t sumsq_blocks(int64_t n);
+hipError_t launch_sumsq(const float* Delta, int64_t n, int64_t ldd, int n_mat, int64_t stride, float* part,
+                        float* out, hipStream_t s);
 
 // Gradient components the stress kernels store per point in the tile
 // partials: the p = 2 Gini gradient is (-g, g), so one; p <= 4 has its own

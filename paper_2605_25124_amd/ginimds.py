@@ -42,7 +42,8 @@ class _Instance(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("p", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("Delta", ctypes.c_void_p), ("ldd", ctypes.c_int64), ("Z", ctypes.c_void_p),
                 ("ldz", ctypes.c_int64), ("nu", ctypes.c_double), ("latent", ctypes.c_int),
-                ("eta", ctypes.c_float), ("sigma_hist", ctypes.c_void_p)]
+                ("eta", ctypes.c_float), ("sigma_hist", ctypes.c_void_p),
+                ("delta_sumsq", ctypes.c_void_p), ("ks_hist", ctypes.c_void_p)]
 
 
 class _Profile(ctypes.Structure):
@@ -74,13 +75,14 @@ def _load():
     L.gini_weight_table.restype = ctypes.c_int
     L.gini_rank.argtypes = [P, P, i64, i32, i64, P, i64, P]
     L.gini_dissim.argtypes = [P, P, i64, i32, i64, P, i32, P, i64, i64, P]
+    L.gini_sumsq.argtypes = [P, P, i64, i64, i32, i64, P, P]
     L.gini_stress_fwd.argtypes = [P, P, i64, i64, P, i32, i64, f64, ctypes.c_int, P, P]
     L.gini_stress_bwd.argtypes = [P, P, i64, i64, P, i32, i64, f64, ctypes.c_int, P, P, i64, P, P]
     L.gini_mds_solve.argtypes = [P, ctypes.POINTER(_Instance), i32, ctypes.POINTER(_Opts), P]
     L.gini_autotune.argtypes = [P, ctypes.POINTER(_Instance), i32, i32, ctypes.POINTER(_Opts), P]
     L.gini_profile_enable.argtypes = [P, ctypes.c_int]
     L.gini_profile_read.argtypes = [P, ctypes.POINTER(_Profile)]
-    for fn in ("gini_create", "gini_rank", "gini_dissim", "gini_stress_fwd", "gini_stress_bwd",
+    for fn in ("gini_create", "gini_rank", "gini_dissim", "gini_sumsq", "gini_stress_fwd", "gini_stress_bwd",
                "gini_mds_solve", "gini_autotune", "gini_profile_enable", "gini_profile_read"):
         getattr(L, fn).restype = ctypes.c_int
     return L
@@ -206,6 +208,26 @@ def gini_dissim(X: torch.Tensor, nus: Sequence[float], out: Optional[torch.Tenso
     return out
 
 
+def gini_sumsq(Delta: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """sum_{i<j} Delta_ij^2 of an n x n matrix or a (k, n, n) stack: a (k, 2)
+    device tensor of (hi, lo) pairs (k = 1 for a single matrix)."""
+    dev = _dev_index(Delta)
+    D3 = Delta.unsqueeze(0) if Delta.dim() == 2 else Delta
+    if D3.dim() != 3 or D3.shape[1] != D3.shape[2]:
+        raise ValueError("Delta must be n x n or k x n x n")
+    if D3.dtype != torch.float32 or (D3.shape[1] > 1 and D3.stride(2) != 1):
+        raise ValueError("Delta must be FP32 with unit column stride")
+    k, n = int(D3.shape[0]), int(D3.shape[1])
+    ldd = max(int(D3.stride(1)), n) if n > 1 else 1
+    if out is None:
+        out = torch.empty((k, 2), dtype=torch.float32, device=Delta.device)
+    if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != 2 * k:
+        raise ValueError("out must be a contiguous FP32 tensor of 2*k elements")
+    c = context(dev)
+    c.check(_lib.gini_sumsq(c.handle, _ptr(D3), n, ldd, k, int(D3.stride(0)), _ptr(out), _stream(dev)))
+    return out
+
+
 def _check_pair(Delta: torch.Tensor, Z: torch.Tensor):
     if Delta.dim() != 2 or Delta.shape[0] != Delta.shape[1]:
         raise ValueError("Delta must be n x n")
@@ -260,6 +282,16 @@ class Instance:
     latent: int = LATENT_GINI
     eta: float = 0.0
     sigma_hist: Optional[torch.Tensor] = None
+    delta_sumsq: Optional[torch.Tensor] = None   # (hi, lo) from gini_sumsq; needed by ks_hist
+    ks_hist: Optional[torch.Tensor] = None       # per-iteration Kruskal stress
+
+
+def _hist_ptr(t: Optional[torch.Tensor], name: str):
+    if t is None:
+        return None
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous FP32 tensor")
+    return t.data_ptr()
 
 
 def _instances(insts: Sequence[Instance]):
@@ -278,12 +310,11 @@ def _instances(insts: Sequence[Instance]):
         a.Delta, a.ldd = I.Delta.data_ptr(), _mat(I.Delta, "Delta")
         a.Z, a.ldz = I.Z.data_ptr(), _mat(I.Z, "Z")
         a.nu, a.latent, a.eta = float(I.nu), int(I.latent), float(I.eta)
-        if I.sigma_hist is not None:
-            if I.sigma_hist.dtype != torch.float32 or not I.sigma_hist.is_contiguous():
-                raise ValueError("sigma_hist must be a contiguous FP32 tensor")
-            a.sigma_hist = I.sigma_hist.data_ptr()
-        else:
-            a.sigma_hist = None
+        a.sigma_hist = _hist_ptr(I.sigma_hist, "sigma_hist")
+        a.ks_hist = _hist_ptr(I.ks_hist, "ks_hist")
+        if I.delta_sumsq is not None and I.delta_sumsq.numel() < 2:
+            raise ValueError("delta_sumsq must hold (hi, lo)")
+        a.delta_sumsq = _hist_ptr(I.delta_sumsq, "delta_sumsq")
     return arr, dev
 
 
@@ -291,8 +322,9 @@ def gini_mds_solve(insts: Sequence[Instance], iters: int, flags: int = SOLVE_PER
                    grid: int = 0) -> None:
     """Fixed-step gradient descent on every instance (synchronises the stream)."""
     for I in insts:
-        if I.sigma_hist is not None and I.sigma_hist.numel() < iters:
-            raise ValueError("sigma_hist shorter than iters")
+        for h, name in ((I.sigma_hist, "sigma_hist"), (I.ks_hist, "ks_hist")):
+            if h is not None and h.numel() < iters:
+                raise ValueError(f"{name} shorter than iters")
     arr, dev = _instances(insts)
     opts = _Opts(int(iters), int(flags), int(tile), int(grid))
     c = context(dev)

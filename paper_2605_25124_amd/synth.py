@@ -11,7 +11,7 @@ Workloads (the paper's datasets are not available, these stand in for their
 shapes and value distributions):
 
 * ``workload_small``   : 200 x 10 iid N(0,1) in FP64 with 5 % of rows scaled by
-  10 (the outlier contamination of the UCI experiments, Section 4.1), nu=2,
+  10 (the outlier contamination of the UCI experiments, Section V-A), nu=2,
   p=2, 100 iterations.
 * ``workload_gmm``     : 2000 x 16 three-component Gaussian mixture
   (means ~ N(0, 4I), unit covariance) plus 10 % uniform outliers in
@@ -19,13 +19,13 @@ shapes and value distributions):
 * ``workload_images``  : 10000 x 784 image-like rows (28 x 28 grids with 1-3
   Gaussian blobs, the brightest 20 % of pixels quantised to uint8, plus
   N(0, 32^2) noise clipped to [0, 255]), heavy ties at 0 and 255; a
-  stand-in for the shape of the MNIST experiment (Section 4.2), nu=2, p=2,
+  stand-in for the shape of the MNIST experiment (Section V-B), nu=2, p=2,
   300 iterations.
 * ``workload_sweep``   : 16 Gaussian-mixture problems, n ~ U{100..3000},
   m ~ U{4..64}, 5 % outliers, each at 8 values of nu in [1.1, 4]
   (128 instances, the nu-sweep of Algorithm 1), p=2, 200 iterations.
 * ``workload_heavy``   : 50000 x 64 iid Student-t(3) (heavy-tailed, as in the
-  simulations of Section 4.3), nu=2, p=3, 100 iterations.
+  simulations of Section V-C), nu=2, p=3, 100 iterations.
 """
 from __future__ import annotations
 

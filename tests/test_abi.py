@@ -147,11 +147,38 @@ def test_solve_validation(gm):
     assert "share Z" in _err(gm, h)
     assert run([inst(Z=0x2000, hist=0x5000), inst(Z=0x3000, hist=0x5000)], ok) == EINVAL
     assert run([inst(Z=0x2000, p=2), inst(Z=0x3000, p=3)], ok) == EUNSUPPORTED
+    k = inst()
+    k.ks_hist = 0x6000                                    # Kruskal history without its normaliser
+    assert run([k], ok) == EINVAL
+    assert "delta_sumsq" in _err(gm, h)
+    k1, k2 = inst(Z=0x2000), inst(Z=0x3000)
+    k1.ks_hist = k2.ks_hist = 0x6000
+    k1.delta_sumsq = k2.delta_sumsq = 0x7000
+    assert run([k1, k2], ok) == EINVAL
+    assert "share ks_hist" in _err(gm, h)
     assert run([inst()], Opts(-1, gm.SOLVE_PERSISTENT, 0, 0)) == EINVAL
     assert run([inst()], Opts(5, gm.SOLVE_PERSISTENT | gm.SOLVE_PLAIN, 0, 0)) == EINVAL
     assert run([inst()], Opts(5, gm.SOLVE_PERSISTENT, 100, 0)) == EINVAL
     assert run([inst()], Opts(5, 1 << 10, 0, 0)) == EINVAL
     assert L.gini_mds_solve(h, None, 1, ctypes.byref(ok), None) == EINVAL
+    L.gini_destroy(h)
+
+
+def test_sumsq_validation(gm):
+    L, h = gm._lib, _ctx(gm)
+    D = ctypes.c_void_p(0x1000)
+    out = ctypes.c_void_p(0x2000)
+    cases = [((h, D, 0, 4, 1, 0, out, None), "n = 0"),
+             ((h, D, 10, 9, 1, 0, out, None), "ldd"),
+             ((h, None, 10, 10, 1, 0, out, None), "non-null"),
+             ((h, D, 10, 10, 1, 0, None, None), "non-null"),
+             ((h, D, 10, 10, 0, 100, out, None), "n_mat"),
+             ((h, D, 10, 10, 70000, 100, out, None), "n_mat"),
+             ((h, D, 10, 10, 2, 99, out, None), "stride")]
+    for args, msg in cases:
+        assert L.gini_sumsq(*args) == EINVAL, msg
+        assert msg in _err(gm, h), (msg, _err(gm, h))
+    assert L.gini_sumsq(None, D, 10, 10, 1, 0, out, None) == EINVAL
     L.gini_destroy(h)
 
 

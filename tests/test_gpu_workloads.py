@@ -1,0 +1,249 @@
+"""Parity at the full workload sizes, in the launch configurations the benchmark
+times: image rows (n=10000, m=784), the Gaussian mixture (n=2000, m=16), the
+128-instance nu-sweep and the heavy-tailed set (n=50000, m=64, p=3).
+
+Where the oracle cannot afford every output (Delta at n=10000 and 50000) it is
+compared on sampled entries, computed one by one; the stress and the gradient
+are compared in full wherever the oracle finishes in seconds, and otherwise on
+sampled gradient rows and on a 2000-point sub-problem."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2605_25124_amd import synth
+from tests._util import assert_dissim_close, dissim_scale, rel
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def gm():
+    from paper_2605_25124_amd import ginimds
+    return ginimds
+
+
+def _sample_pairs(n, k, seed, tile=32):
+    """k random off-diagonal pairs plus pairs on tile seams and at the ends."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    pi = g.integers(0, n, k)
+    pj = g.integers(0, n, k)
+    edge = [(0, 1), (0, n - 1), (n - 2, n - 1), (tile - 1, tile), (tile, 2 * tile - 1),
+            (n - 1 - tile, n - 1), (n // 2, n // 2 + 1)]
+    pi = np.concatenate([pi, [a for a, _ in edge]])
+    pj = np.concatenate([pj, [b for _, b in edge]])
+    keep = pi != pj
+    return pi[keep], pj[keep]
+
+
+def _check_sampled_dissim(gm, orc, X32, D, nus, k, seed, what):
+    n = X32.shape[0]
+    pi, pj = _sample_pairs(n, k, seed)
+    ti, tj = torch.from_numpy(pi).to(DEV), torch.from_numpy(pj).to(DEV)
+    ref = orc.dissim_pairs(X32, pi, pj, nus, orc.MATCH32)
+    for q, nu in enumerate(nus):
+        got = D[q][ti, tj].cpu().numpy()
+        mir = D[q][tj, ti].cpu().numpy()
+        assert np.array_equal(got, mir), f"{what}: mirror not bitwise equal at nu={nu}"
+        S = dissim_scale(orc, X32, list(zip(pi, pj)), nu)
+        assert_dissim_close(got, ref[:, q], S, 1e-5, f"{what} nu={nu}")
+        assert float(D[q].diagonal().abs().max()) == 0.0
+
+
+def _one_step(gm, D, Z0, nu, flags, tile, latent=0):
+    Z = Z0.clone()
+    h = torch.zeros(1, device=DEV)
+    gm.gini_mds_solve([gm.Instance(D, Z, nu, latent, 0.0, h)], 1, flags, tile)
+    return Z, float(h[0])
+
+
+def _check_step(orc, n, p, nu, Z0, Z1, s_gpu, s_ref, G_ref, what, latent=0):
+    eta = orc.step_size(n, p, nu, latent)
+    assert abs(s_gpu - s_ref) <= 1e-4 * s_ref, (what, s_gpu, s_ref)
+    step = (Z0.cpu().numpy().astype(np.float64) - Z1.cpu().numpy().astype(np.float64)) / eta
+    assert rel(step, G_ref) <= 1e-4, (what, rel(step, G_ref))
+
+
+# ------------------------------------------------------------------ image rows
+@pytest.fixture(scope="module")
+def images(gm):
+    w = synth.workload_images()
+    X = torch.from_numpy(w.X).to(DEV)
+    D = gm.gini_dissim(X, [2.0, 3.7])
+    torch.cuda.synchronize()
+    return w, D
+
+
+def test_images_dissim_sampled(gm, orc, images):
+    w, D = images
+    _check_sampled_dissim(gm, orc, w.X, D, [2.0, 3.7], 1500, 11, "images n=10000 m=784")
+
+
+def test_images_descent_step_at_bench_configs(gm, orc, images):
+    """One descent step in each launch configuration the benchmark can time,
+    against the oracle's full stress and gradient at n=10000."""
+    w, D = images
+    D2 = D[0]
+    n = w.X.shape[0]
+    Z0 = torch.from_numpy(w.Z0[0]).to(DEV)
+    s_ref, G_ref = orc.stress(D2.cpu().numpy(), w.Z0[0], 2.0, 0, orc.MATCH32)
+    configs = [(gm.SOLVE_BATCHED, 64), (gm.SOLVE_BATCHED, 128), (gm.SOLVE_BATCHED, 256),
+               (gm.SOLVE_PERSISTENT, 128), (gm.SOLVE_PLAIN, 128)]
+    outs = []
+    for flags, tile in configs:
+        Z1, s = _one_step(gm, D2, Z0, 2.0, flags, tile)
+        _check_step(orc, n, 2, 2.0, Z0, Z1, s, s_ref, G_ref, f"flags={flags} tile={tile}")
+        outs.append((tile, Z1, s))
+    for tile, Z1, s in outs:                    # same tile: bitwise equal across modes
+        for t2, Z2, s2 in outs:
+            if t2 == tile:
+                assert torch.equal(Z1, Z2) and s == s2
+    best = gm.gini_autotune([gm.Instance(D2, Z0.clone(), 2.0)], 10)
+    Z1, s = _one_step(gm, D2, Z0, 2.0, best["flags"], best["tile"])
+    _check_step(orc, n, 2, 2.0, Z0, Z1, s, s_ref, G_ref, f"autotuned {best}")
+
+
+def test_images_full_run_descends(gm, orc, images):
+    """300 iterations at n=10000, nu=3.7: the stress never rises (the p=2 Gini
+    step is a one-dimensional Guttman step), and the last iterate's stress and
+    gradient match the oracle evaluated at that iterate."""
+    w, D = images
+    D3 = D[1]
+    Z = torch.from_numpy(w.Z0[0]).to(DEV)
+    h = torch.zeros(w.iters, device=DEV)
+    gm.gini_mds_solve([gm.Instance(D3, Z, 3.7, 0, 0.0, h)], w.iters, gm.SOLVE_BATCHED, 128)
+    hist = h.cpu().numpy().astype(np.float64)
+    assert np.all(np.diff(hist) <= 1e-5 * hist[0])
+    assert hist[-1] < hist[0]
+    G, sig = gm.gini_stress_bwd(D3, Z, 3.7, 0)
+    s_ref, G_ref = orc.stress(D3.cpu().numpy(), Z.cpu().numpy(), 3.7, 0, orc.MATCH32)
+    assert abs(float(sig[0].double() + sig[1].double()) - s_ref) <= 1e-4 * s_ref
+    assert rel(G.cpu().numpy(), G_ref) <= 1e-4
+
+
+# --------------------------------------- Gaussian mixture, n=2000, m=16
+def test_gmm_full(gm, orc):
+    w = synth.workload_gmm()
+    n = w.X.shape[0]
+    X = torch.from_numpy(w.X).to(DEV)
+    D = gm.gini_dissim(X, w.nus)
+    torch.cuda.synchronize()
+    _check_sampled_dissim(gm, orc, w.X, D, w.nus, 6000, 12, "gmm n=2000 m=16")
+    ref = orc.dissim(w.X, w.nus, orc.MATCH32)
+    for q in range(len(w.nus)):                 # every entry, against a global scale
+        Dg = D[q].cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(Dg - ref[q])) <= 1e-5 * np.max(np.abs(ref[q]))
+    insts, hs, Zs = [], [], []
+    for q, nu in enumerate(w.nus):
+        Z0 = torch.from_numpy(w.Z0[q]).to(DEV)
+        s_ref, G_ref = orc.stress(D[q].cpu().numpy(), w.Z0[q], nu, 0, orc.MATCH32)
+        Z1, s = _one_step(gm, D[q], Z0, nu, gm.SOLVE_BATCHED, 128)
+        _check_step(orc, n, 2, nu, Z0, Z1, s, s_ref, G_ref, f"gmm nu={nu}")
+        Z = Z0.clone()
+        h = torch.zeros(w.iters, device=DEV)
+        insts.append(gm.Instance(D[q], Z, nu, 0, 0.0, h))
+        hs.append(h)
+        Zs.append(Z)
+    gm.gini_mds_solve(insts, w.iters, gm.SOLVE_BATCHED, 128)
+    for q, nu in enumerate(w.nus):
+        hist = hs[q].cpu().numpy().astype(np.float64)
+        assert np.all(np.diff(hist) <= 1e-5 * hist[0]), nu
+    # nu = 2: the trajectory against the oracle's own descent over 100 steps
+    q = w.nus.index(2.0)
+    Z = torch.from_numpy(w.Z0[q]).to(DEV)
+    h = torch.zeros(100, device=DEV)
+    gm.gini_mds_solve([gm.Instance(D[q], Z, 2.0, 0, 0.0, h)], 100, gm.SOLVE_BATCHED, 128)
+    _, href = orc.solve(D[q].cpu().numpy(), w.Z0[q], 2.0, 100, 0, orc.MATCH32)
+    hist = h.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(hist - href)) <= 1e-3 * href[0]
+
+
+# ------------------------------------------------ nu-sweep, 128 instances
+def test_sweep_full(gm, orc):
+    """All 128 instances of the sweep in one batched launch: the first step of
+    every instance against the oracle, and all modes bitwise equal."""
+    probs = synth.workload_sweep()
+    Ds = []
+    for pr in probs:
+        Ds.append(gm.gini_dissim(torch.from_numpy(pr.X).to(DEV), pr.nus))
+    torch.cuda.synchronize()
+
+    def make():
+        insts, hs = [], []
+        for pr, D in zip(probs, Ds):
+            for q, nu in enumerate(pr.nus):
+                h = torch.zeros(3, device=DEV)
+                insts.append(gm.Instance(D[q], torch.from_numpy(pr.Z0[q]).to(DEV), nu, 0, 0.0, h))
+                hs.append(h)
+        return insts, hs
+
+    tuned = gm.gini_autotune(make()[0], 10)
+    runs = {}
+    for name, flags, tile in [("auto", tuned["flags"], tuned["tile"]),
+                              ("batched", gm.SOLVE_BATCHED, tuned["tile"]),
+                              ("plain", gm.SOLVE_PLAIN, tuned["tile"])]:
+        insts, hs = make()
+        gm.gini_mds_solve(insts, 3, flags, tile, tuned["grid"] if name == "auto" else 0)
+        runs[name] = ([I.Z.cpu() for I in insts], [h.cpu() for h in hs])
+    for name in ("batched", "plain"):
+        for a, b in zip(runs["auto"][0], runs[name][0]):
+            assert torch.equal(a, b), name
+        for a, b in zip(runs["auto"][1], runs[name][1]):
+            assert torch.equal(a, b), name
+    insts, hs = make()
+    gm.gini_mds_solve(insts, 1, tuned["flags"], tuned["tile"], tuned["grid"])
+    k = 0
+    for pr, D in zip(probs, Ds):
+        n = pr.X.shape[0]
+        for q, nu in enumerate(pr.nus):
+            s_ref, G_ref = orc.stress(D[q].cpu().numpy(), pr.Z0[q], nu, 0, orc.MATCH32)
+            Z0 = torch.from_numpy(pr.Z0[q])
+            _check_step(orc, n, 2, nu, Z0, insts[k].Z, float(hs[k][0]), s_ref, G_ref, f"{pr.name} nu={nu}")
+            k += 1
+
+
+# ------------------------------------------------------- heavy tails, n=50000
+def test_heavy_full(gm, orc):
+    """n=50000, m=64, p=3 (Delta 10 GB): sampled Delta entries; sampled gradient
+    rows at full size; 100 iterations through the autograd Function with stress
+    and gradient checked on a 2000-point sub-problem at t = 0, 50, 100."""
+    w = synth.workload_heavy()
+    n, p, nu = w.X.shape[0], w.p, w.nus[0]
+    D = gm.gini_dissim(torch.from_numpy(w.X).to(DEV), [nu])
+    torch.cuda.synchronize()
+    _check_sampled_dissim(gm, orc, w.X, D, [nu], 3000, 13, "heavy n=50000 m=64")
+    D = D[0]
+    rows = np.array([0, 1, 255, 256, 31337, n - 2, n - 1], dtype=np.int64)
+    trows = torch.from_numpy(rows).to(DEV)
+    Drows = D.index_select(0, trows).cpu().numpy()
+    S = torch.from_numpy(np.sort(synth.subsample(n, 2000, 5))).to(DEV)
+    Dsub = D.index_select(0, S).index_select(1, S).contiguous()
+    Dsub_h = Dsub.cpu().numpy()
+    eta = orc.step_size(n, p, nu, 0)
+    Z = torch.from_numpy(w.Z0[0]).to(DEV).requires_grad_(True)
+    sig0 = None
+    for t in range(w.iters + 1):
+        if t in (0, 50, w.iters):
+            with torch.no_grad():
+                Gf, sf = gm.gini_stress_bwd(D, Z.detach(), nu, 0)
+                Zh = Z.detach().cpu().numpy()
+                G_ref, _ = orc.grad_rows(Drows, rows, Zh, nu, 0, orc.MATCH32)
+                assert rel(Gf.cpu().numpy()[rows], G_ref) <= 1e-4, t
+                Zs = Z.detach().index_select(0, S).contiguous()
+                Gs, ss = gm.gini_stress_bwd(Dsub, Zs, nu, 0)
+                s_ref, Gs_ref = orc.stress(Dsub_h, Zs.cpu().numpy(), nu, 0, orc.MATCH32)
+                assert abs(float(ss[0].double() + ss[1].double()) - s_ref) <= 1e-4 * s_ref, t
+                assert rel(Gs.cpu().numpy(), Gs_ref) <= 1e-4, t
+        if t == w.iters:
+            break
+        loss = gm.GiniStress.apply(D, Z, nu, 0)
+        loss.backward()
+        if t == 0:
+            sig0 = float(loss)
+            assert abs(sig0 - float(sf[0].double() + sf[1].double())) <= 1e-6 * sig0
+        with torch.no_grad():
+            Z -= eta * Z.grad
+        Z.grad = None
+    with torch.no_grad():
+        s_end = gm.gini_stress_fwd(D, Z.detach(), nu, 0)
+    assert float(s_end[0].double() + s_end[1].double()) < sig0

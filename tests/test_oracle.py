@@ -259,6 +259,26 @@ def test_zero_residual_fixed_point(orc, nu):
     assert np.all(G == 0.0)
 
 
+@pytest.mark.parametrize("latent", [0, 1])
+def test_kruskal_stress_pins(orc, latent):
+    """Kruskal stress (Section IV-B): a collapsed configuration (all latent
+    distances 0) has sigma equal to the normaliser, so KS = 1 exactly; the
+    zero-residual configuration has KS = 0; and KS is scale free under the
+    Euclidean latent distance (Delta and Z scaled together)."""
+    X, Z = _problem(31, 26, 4, 2)
+    D = orc.dissim(X, [2.0], orc.EXACT)[0]
+    assert orc.kruskal(D, np.zeros_like(Z), 2.0, latent, orc.EXACT) == 1.0
+    g = np.random.Generator(np.random.PCG64(56))
+    Y = g.standard_normal((15, 2))
+    DY = orc.dissim(Y, [2.0], orc.EXACT)[0]
+    assert orc.kruskal(DY, Y, 2.0, orc.LATENT_GINI, orc.EXACT) == 0.0
+    if latent == 1:
+        k1 = orc.kruskal(D, Z, 2.0, latent, orc.EXACT)
+        k2 = orc.kruskal(3.5 * D, 3.5 * Z, 2.0, latent, orc.EXACT)
+        assert k2 == pytest.approx(k1, rel=1e-13)
+        assert 0.0 < k1 < 10.0
+
+
 @pytest.mark.parametrize("latent,p", [(0, 2), (0, 3), (1, 2)])
 def test_gradient_translation_invariance(orc, latent, p):
     X, Z = _problem(8, 40, 5, p)
@@ -271,7 +291,7 @@ def test_gradient_translation_invariance(orc, latent, p):
 
 
 def test_euclid_step_is_guttman_transform(orc):
-    """SMACOF (Section 3.2, unit weights): Z - grad/(2n) = B(Z) Z / n + centroid."""
+    """SMACOF (Section IV-B, unit weights): Z - grad/(2n) = B(Z) Z / n + centroid."""
     X, Z = _problem(9, 22, 5, 2)
     n = 22
     D = orc.dissim(X, [2.0], orc.EXACT)[0]
