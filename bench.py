@@ -20,8 +20,10 @@ Printed as ONE JSON line:
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -51,6 +53,27 @@ def parse():
                     help="only run a plain device copy of 256 MiB (calibration of memory counters)")
     ap.add_argument("--sweep-tile", type=int, default=0)
     return ap.parse_args()
+
+
+PROFILE = os.path.join(ROOT, "profiles", "k_stress_units_images_n10000.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2605_25124_amd", "csrc", f)
+                  for f in ("k_stress.hip", "common.hpp", "kernels.hpp")]
+
+
+def measured_traffic(kernel, n, tile):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when that summary was taken on other kernel sources or
+    another launch configuration."""
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    fields = dict(re.findall(r"^(\w+): (\S+)$", text, re.M))
+    digest = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()
+    if (fields.get("kernel") != kernel or fields.get("source_sha256") != digest
+            or fields.get("n") != str(n) or fields.get("tile") != str(tile)):
+        return None
+    return float(fields["traffic_bytes_per_launch"])
 
 
 def log(msg):
@@ -150,7 +173,9 @@ def main():
         avg_ms = prof["persistent_ms"] / max(args.steps, 1)
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": kname,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(kname, n, best["tile"]) if mode_name == "batched" else None,
+            "kernel": kname,
             "avg_launch_us": round(avg_ms * 1e3, 2), "alg_bytes_per_launch": alg_bytes,
             "reduce_avg_us": round(prof["reduce_ms"] * 1e3 / max(prof["reduce_launches"], 1), 2)}
     log(f"roofline {kname}: {avg_ms * 1e3:.1f} us/launch -> {achieved:.0f} GB/s")

@@ -23,6 +23,8 @@
 // gradient or takes the descent step.  No floating-point
 // atomics anywhere: results are bitwise reproducible and independent of
 // scheduling and of how many instances share a launch.
+#include <hip/hip_ext.h>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -31,8 +33,6 @@ namespace gmds {
 constexpr int kWG = 256;
 constexpr int kLPR = 16;                 // lanes per tile row = one DPP row
 constexpr int kRPS = kWG / kLPR;         // rows per step
-constexpr int kUR = 64;                  // rows per work unit
-constexpr int kUnitSteps = kUR / kRPS;   // steps per unit
 constexpr int kSplit = 16;               // interleaved partial sums per point in the reduction
 constexpr int kBatch = 8;                // loads in flight per partial sum
 constexpr int kWaves = kStressWaves;     // waves per workgroup (one stress partial each)
@@ -49,7 +49,12 @@ __device__ __forceinline__ gflw* gpw(float* p) { return (gflw*)p; }
 template <int T> struct TileShape {
     static constexpr int CPT = T / kLPR;      // columns per thread
     static constexpr int NQ = CPT / 4;        // 16-byte loads per thread and row
-    static constexpr int UNITS = T / kUR;     // work units per tile
+    static constexpr int UR = 64;             // rows per work unit
+    static constexpr int STEPS = UR / kRPS;   // pipelined steps per unit
+    static constexpr int UNITS = T / UR;      // work units per tile
+    // Delta steps in flight per thread: the whole unit while that costs at
+    // most 8 loads (32 registers), else two
+    static constexpr int DEPTH = (NQ * STEPS <= 8) ? STEPS : 2;
 };
 
 template <int P, int LAT>
@@ -89,6 +94,40 @@ __device__ __forceinline__ float pair_term(const float (&zi)[P], const float (&z
         float r = fmaf(D.c2, fabsf(w), -d);
         if constexpr (MASK) r = valid ? r : 0.f;
         if constexpr (GRAD) g[0] = (w > 0.f) ? r : ((w < 0.f) ? -r : 0.f);
+        return r * r;
+    } else if constexpr (P == 3 && LAT == 0) {
+        // Untied u takes the doubled midranks (2, 4, 6) in sorted order, and the
+        // middle weight is exactly 0, so delta = a_max u_max + a_min u_min with
+        // a_max = (3/2) W_3[6] = -a_min.  A tie (rare) takes the general rule.
+        const float mx = fmaxf(fmaxf(u[0], u[1]), u[2]);
+        const float mn = fminf(fminf(u[0], u[1]), u[2]);
+        const bool tie = (u[0] == u[1]) || (u[1] == u[2]) || (u[0] == u[2]);
+        float r, a[3];
+        if (!tie) {
+            const float wmax = D.wtab[4], wmin = D.wtab[0];
+            r = fmaf(wmax, mx, wmin * mn) - d;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a[c] = (u[c] == mx) ? wmax : ((u[c] == mn) ? wmin : 0.f);
+        } else {
+            float delta = 0.f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                int t = 1;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) t += (u[k] < u[c]) ? 2 : ((u[k] == u[c]) ? 1 : 0);
+                float w = D.wtab[0];
+#pragma unroll
+                for (int q = 1; q < 5; ++q) w = (t - 2 == q) ? D.wtab[q] : w;
+                a[c] = w;
+                delta = fmaf(u[c], w, delta);
+            }
+            r = delta - d;
+        }
+        if constexpr (MASK) r = valid ? r : 0.f;
+        if constexpr (GRAD) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) g[c] = r * a[c];
+        }
         return r * r;
     } else if constexpr (LAT == 0) {
         float a[P];
@@ -162,7 +201,7 @@ __device__ Comp wg_sum(Comp v, float* lds) {
 // column reduction (16 row groups x T) and the stress tree.
 template <int P, int T>
 constexpr int unit_lds_floats() {
-    return kUR * P + T * P + (kRPS * T > 2 * kWG ? kRPS * T : 2 * kWG);
+    return TileShape<T>::UR * P + T * P + (kRPS * T > 2 * kWG ? kRPS * T : 2 * kWG);
 }
 
 // Stream unit `sub` (rows I*T + sub*UR ..) of tile lt = (I, J) of instance D:
@@ -173,45 +212,20 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
     constexpr int CPT = TileShape<T>::CPT;
     constexpr int NQ = TileShape<T>::NQ;
     constexpr int UNITS = TileShape<T>::UNITS;
+    constexpr int UR = TileShape<T>::UR;
+    constexpr int STEPS = TileShape<T>::STEPS;
     constexpr int PG = PG_<P, LAT>::value;
     const int tid = threadIdx.x;
     const int c4 = tid % kLPR;
     const int rr = tid / kLPR;
     const int64_t n = D.n;
-    const int64_t i0 = I * T + sub * kUR;
+    const int64_t i0 = I * T + sub * UR;
     const int64_t j0 = J * T;
     const int p = (P == kMaxP) ? D.p : P;
     gfl* Zg = gp(D.Z);
-    float* zrow = lds;                                  // [kUR][P]
-    float* zcol = lds + kUR * P;                        // [T][P]
+    float* zrow = lds;                                  // [UR][P]
+    float* zcol = lds + UR * P;                         // [T][P]
     float* red = zcol + T * P;
-
-    // latent rows and columns of this unit into LDS (coalesced), then the
-    // thread's columns into registers
-    for (int x = tid; x < kUR * P; x += kWG) {
-        const int r = x / P, c = x % P;
-        const int64_t i = i0 + r;
-        zrow[x] = (c < p && (!MASK || i < n)) ? Zg[i * D.ldz + c] : 0.f;
-    }
-    for (int x = tid; x < T * P; x += kWG) {
-        const int r = x / P, c = x % P;
-        const int64_t j = j0 + r;
-        zcol[x] = (c < p && (!MASK || j < n)) ? Zg[j * D.ldz + c] : 0.f;
-    }
-    __syncthreads();
-    float zj[CPT][P];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-            for (int c = 0; c < P; ++c) zj[q * 4 + e][c] = zcol[(4 * (c4 + q * kLPR) + e) * P + c];
-    float colacc[CPT][PG];
-#pragma unroll
-    for (int x = 0; x < CPT; ++x)
-#pragma unroll
-        for (int c = 0; c < PG; ++c) colacc[x][c] = 0.f;
-    Comp sig;
 
     // Delta loads for one step of the unit (unmasked: 16-byte global loads)
     auto load_step = [&](int s, f4v (&buf)[NQ]) {
@@ -238,8 +252,54 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
             }
         }
     };
+    // The latent rows and columns of the unit are requested first (coalesced),
+    // then the first DEPTH steps of Delta, so that both are in flight together
+    // while the coordinates wait for their LDS slots; afterwards step
+    // s + DEPTH is loaded into the slot that step s has just been computed from.
+    constexpr int NZR = (UR * P + kWG - 1) / kWG;
+    constexpr int NZC = (T * P + kWG - 1) / kWG;
+    float zr_[NZR], zc_[NZC];
+#pragma unroll
+    for (int k = 0; k < NZR; ++k) {
+        const int x = tid + k * kWG;
+        const int r = x / P, c = x % P;
+        const int64_t i = i0 + r;
+        zr_[k] = (x < UR * P && c < p && (!MASK || i < n)) ? Zg[i * D.ldz + c] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < NZC; ++k) {
+        const int x = tid + k * kWG;
+        const int r = x / P, c = x % P;
+        const int64_t j = j0 + r;
+        zc_[k] = (x < T * P && c < p && (!MASK || j < n)) ? Zg[j * D.ldz + c] : 0.f;
+    }
+    constexpr int DEPTH = TileShape<T>::DEPTH;
+    f4v buf[DEPTH][NQ];
+#pragma unroll
+    for (int s = 0; s < DEPTH; ++s) load_step(s, buf[s]);
+#pragma unroll
+    for (int k = 0; k < NZR; ++k)
+        if (tid + k * kWG < UR * P) zrow[tid + k * kWG] = zr_[k];
+#pragma unroll
+    for (int k = 0; k < NZC; ++k)
+        if (tid + k * kWG < T * P) zcol[tid + k * kWG] = zc_[k];
+    __syncthreads();
+    float zj[CPT][P];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int c = 0; c < P; ++c) zj[q * 4 + e][c] = zcol[(4 * (c4 + q * kLPR) + e) * P + c];
+    float colacc[CPT][PG];
+#pragma unroll
+    for (int x = 0; x < CPT; ++x)
+#pragma unroll
+        for (int c = 0; c < PG; ++c) colacc[x][c] = 0.f;
+    Comp sig;
+
     auto compute_step = [&](int s, const f4v (&buf)[NQ]) {
-        const int il = sub * kUR + s * kRPS + rr;          // row within the tile
+        const int il = sub * UR + s * kRPS + rr;           // row within the tile
         const int64_t i = I * T + il;
         float zi[P];
 #pragma unroll
@@ -275,16 +335,10 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
         sig.add(sst);
     };
 
-    f4v b0[NQ], b1[NQ];
-    load_step(0, b0);
 #pragma unroll
-    for (int s = 0; s < kUnitSteps; s += 2) {
-        if (s + 1 < kUnitSteps) load_step(s + 1, b1);
-        compute_step(s, b0);
-        if (s + 1 < kUnitSteps) {
-            if (s + 2 < kUnitSteps) load_step(s + 2, b0);
-            compute_step(s + 1, b1);
-        }
+    for (int s = 0; s < STEPS; ++s) {
+        compute_step(s, buf[s % DEPTH]);
+        if (s + DEPTH < STEPS) load_step(s + DEPTH, buf[s % DEPTH]);
     }
 
     if constexpr (GRAD) {
@@ -327,7 +381,7 @@ __device__ __forceinline__ void stress_unit(const InstDesc& D, int64_t lu, float
     const int sub = (int)(lu % UNITS);
     int64_t I, J;
     tri_decode(lt, D.nb, I, J);
-    if (I * T + (int64_t)sub * kUR >= D.n) return;          // rows past n: nothing to do
+    if (I * T + (int64_t)sub * TileShape<T>::UR >= D.n) return;   // rows past n: nothing to do
     const bool interior = D.vec && (I < J) && ((J + 1) * T <= D.n);
     if (interior) unit_body<P, LAT, T, GRAD, false>(D, lt, sub, I, J, lds);
     else unit_body<P, LAT, T, GRAD, true>(D, lt, sub, I, J, lds);
@@ -373,7 +427,7 @@ __device__ __forceinline__ void point_partial(const InstDesc& D, int64_t k, int 
                 const int u = (int)(tc % UNITS);
                 const int64_t lt = tri_index(I, b, nb);
                 // units past n (only in the last tile) were never written
-                const bool ok = (t < nterm) && !(lt == last_lt && I * T + (int64_t)u * kUR >= D.n);
+                const bool ok = (t < nterm) && !(lt == last_lt && I * T + (int64_t)u * TileShape<T>::UR >= D.n);
 #pragma unroll
                 for (int c = 0; c < PG; ++c) v[q][c] = ok ? -cp[((lt * UNITS + u) * T + kl) * PG + c] : 0.f;
             }
@@ -393,6 +447,20 @@ template <int P, int LAT, int T, int NT>
 __device__ void reduce_group(const InstDesc& D, int64_t k0, int mode, float* lds) {
     constexpr int PG = PG_<P, LAT>::value;
     const int tid = threadIdx.x;
+    const int p = (P == kMaxP) ? D.p : P;
+    // the combining threads fetch what they update before the partial sums
+    // arrive, so that its latency overlaps theirs
+    const bool comb = tid < kNPT && k0 + tid < D.n;
+    float zold[P];
+    float sc = 1.f;
+    if (comb) {
+        if (mode == kModeGrad) {
+            if (D.grad_out) sc = *D.grad_out;
+        } else {
+#pragma unroll
+            for (int c = 0; c < P; ++c) zold[c] = (c < p) ? D.Z[(k0 + tid) * D.ldz + c] : 0.f;
+        }
+    }
     for (int item = tid; item < kSplit * kNPT; item += NT) {
         const int sp = item / kNPT;
         const int pl = item % kNPT;
@@ -406,7 +474,7 @@ __device__ void reduce_group(const InstDesc& D, int64_t k0, int mode, float* lds
         }
     }
     __syncthreads();
-    if (tid < kNPT && k0 + tid < D.n) {
+    if (comb) {
         const int pl = tid;
         const int64_t k = k0 + pl;
         Comp tot[PG];
@@ -427,16 +495,14 @@ __device__ void reduce_group(const InstDesc& D, int64_t k0, int mode, float* lds
 #pragma unroll
             for (int c = 0; c < P; ++c) G[c] = 2.f * tot[c].value();
         }
-        const int p = (P == kMaxP) ? D.p : P;
         if (mode == kModeGrad) {
-            const float sc = D.grad_out ? *D.grad_out : 1.f;
 #pragma unroll
             for (int c = 0; c < P; ++c)
                 if (c < p) D.gradZ[k * D.ldg + c] = sc * G[c];
         } else {
 #pragma unroll
             for (int c = 0; c < P; ++c)
-                if (c < p) D.Z[k * D.ldz + c] -= D.eta * G[c];
+                if (c < p) D.Z[k * D.ldz + c] = zold[c] - D.eta * G[c];
         }
     }
     __syncthreads();
@@ -479,7 +545,7 @@ __device__ Comp sigma_slice(const InstDesc& D, int slice, float* lds) {
                 const int64_t t = t0 + (int64_t)q * kVT;
                 const int64_t lu = t / kWaves;
                 const int u = (int)(lu % UNITS);
-                const bool ok = (t < e) && !(lu / UNITS == nt - 1 && (D.nb - 1) * T + (int64_t)u * kUR >= D.n);
+                const bool ok = (t < e) && !(lu / UNITS == nt - 1 && (D.nb - 1) * T + (int64_t)u * TileShape<T>::UR >= D.n);
                 hv[q] = ok ? sp[2 * t] : 0.f;
                 lv[q] = ok ? sp[2 * t + 1] : 0.f;
             }
@@ -730,31 +796,42 @@ __global__ __launch_bounds__(kWG) void k_solve_persistent(const InstDesc* __rest
 // ------------------------------------------------------------- dispatch
 static int p_bucket(int p) { return p <= 4 ? p : kMaxP; }
 
-template <int P, int LAT, int T>
-static hipError_t units_impl(const InstDesc* dd, int n_inst, int64_t count, int64_t qb, bool grad, hipStream_t s) {
-    if (count <= 0) return hipSuccess;
-    if (grad)
-        hipLaunchKernelGGL((k_stress_units<P, LAT, T, true>), dim3((unsigned)count), dim3(kWG), 0, s, dd, n_inst, qb);
+// A launch on stream s; with both events set (profiling), the runtime stamps
+// them at the start and the end of the kernel itself.
+struct Launch {
+    hipStream_t s;
+    LaunchTimer tm;
+};
+
+template <typename K, typename... A>
+static hipError_t launch_k(K kernel, dim3 grid, dim3 block, const Launch& L, A... args) {
+    if (L.tm.start && L.tm.stop)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, L.s, L.tm.start, L.tm.stop, 0, args...);
     else
-        hipLaunchKernelGGL((k_stress_units<P, LAT, T, false>), dim3((unsigned)count), dim3(kWG), 0, s, dd, n_inst, qb);
+        hipLaunchKernelGGL(kernel, grid, block, 0, L.s, args...);
     return hipGetLastError();
+}
+
+template <int P, int LAT, int T>
+static hipError_t units_impl(const InstDesc* dd, int n_inst, int64_t count, int64_t qb, bool grad, const Launch& L) {
+    if (count <= 0) return hipSuccess;
+    if (grad) return launch_k(k_stress_units<P, LAT, T, true>, dim3((unsigned)count), dim3(kWG), L, dd, n_inst, qb);
+    return launch_k(k_stress_units<P, LAT, T, false>, dim3((unsigned)count), dim3(kWG), L, dd, n_inst, qb);
 }
 
 template <int P, int LAT, int T>
 static hipError_t reduce_impl(const InstDesc* dd, int n_inst, int64_t blocks, int64_t qb, int mode, int it,
-                              hipStream_t s) {
+                              const Launch& L) {
     if (blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_stress_reduce<P, LAT, T>), dim3((unsigned)blocks), dim3(kRedWG), 0, s, dd, n_inst, qb, mode,
-                       it);
-    return hipGetLastError();
+    return launch_k(k_stress_reduce<P, LAT, T>, dim3((unsigned)blocks), dim3(kRedWG), L, dd, n_inst, qb, mode, it);
 }
 
 template <int LAT, int T>
 static hipError_t dispatch_p(int which, const InstDesc* dd, int n_inst, int64_t count, int64_t qb, int p, bool grad,
-                             int64_t max_n, int mode, int it, hipStream_t s) {
+                             int64_t max_n, int mode, int it, const Launch& L) {
 #define GMDS_CALL(PP)                                                                 \
-    return which == 0 ? units_impl<PP, LAT, T>(dd, n_inst, count, qb, grad, s)         \
-                      : reduce_impl<PP, LAT, T>(dd, n_inst, max_n, qb, mode, it, s);  /* max_n: block count */
+    return which == 0 ? units_impl<PP, LAT, T>(dd, n_inst, count, qb, grad, L)         \
+                      : reduce_impl<PP, LAT, T>(dd, n_inst, max_n, qb, mode, it, L);  /* max_n: block count */
     switch (p_bucket(p)) {
         case 1: GMDS_CALL(1)
         case 2: GMDS_CALL(2)
@@ -767,37 +844,42 @@ static hipError_t dispatch_p(int which, const InstDesc* dd, int n_inst, int64_t 
 
 template <int T>
 static hipError_t dispatch_lat(int which, const InstDesc* dd, int n_inst, int64_t count, int64_t qb, int p,
-                               int latent, bool grad, int64_t max_n, int mode, int it, hipStream_t s) {
-    if (latent == 0) return dispatch_p<0, T>(which, dd, n_inst, count, qb, p, grad, max_n, mode, it, s);
-    return dispatch_p<1, T>(which, dd, n_inst, count, qb, p, grad, max_n, mode, it, s);
+                               int latent, bool grad, int64_t max_n, int mode, int it, const Launch& L) {
+    if (latent == 0) return dispatch_p<0, T>(which, dd, n_inst, count, qb, p, grad, max_n, mode, it, L);
+    return dispatch_p<1, T>(which, dd, n_inst, count, qb, p, grad, max_n, mode, it, L);
 }
 
 static hipError_t dispatch(int which, const InstDesc* dd, int n_inst, int64_t count, int64_t qb, int p, int latent,
-                           int T, bool grad, int64_t max_n, int mode, int it, hipStream_t s) {
-    if (T == 64) return dispatch_lat<64>(which, dd, n_inst, count, qb, p, latent, grad, max_n, mode, it, s);
-    if (T == 128) return dispatch_lat<128>(which, dd, n_inst, count, qb, p, latent, grad, max_n, mode, it, s);
-    return dispatch_lat<256>(which, dd, n_inst, count, qb, p, latent, grad, max_n, mode, it, s);
+                           int T, bool grad, int64_t max_n, int mode, int it, const Launch& L) {
+    if (T == 64) return dispatch_lat<64>(which, dd, n_inst, count, qb, p, latent, grad, max_n, mode, it, L);
+    if (T == 128) return dispatch_lat<128>(which, dd, n_inst, count, qb, p, latent, grad, max_n, mode, it, L);
+    return dispatch_lat<256>(which, dd, n_inst, count, qb, p, latent, grad, max_n, mode, it, L);
 }
 
 hipError_t launch_stress_units(const InstDesc* dd, int n_inst, int64_t count, int64_t q_base, int p, int latent, int T,
-                               bool grad, hipStream_t s) {
-    return dispatch(0, dd, n_inst, count, q_base, p, latent, T, grad, 0, 0, 0, s);
+                               bool grad, hipStream_t s, LaunchTimer tm) {
+    return dispatch(0, dd, n_inst, count, q_base, p, latent, T, grad, 0, 0, 0, Launch{s, tm});
 }
 
 hipError_t launch_stress_reduce(const InstDesc* dd, int n_inst, int64_t blocks, int64_t q_base, int p, int latent,
-                                int T, int mode, int it, hipStream_t s) {
-    return dispatch(1, dd, n_inst, 0, q_base, p, latent, T, true, blocks, mode, it, s);
+                                int T, int mode, int it, hipStream_t s, LaunchTimer tm) {
+    return dispatch(1, dd, n_inst, 0, q_base, p, latent, T, true, blocks, mode, it, Launch{s, tm});
 }
 
 // Host mirror of reduce_blocks (must agree with the device functions above).
+int units_per_tile(int T) {
+    if (T == 64) return TileShape<64>::UNITS;
+    if (T == 128) return TileShape<128>::UNITS;
+    return TileShape<256>::UNITS;
+}
+
 int64_t reduce_block_count(int64_t n, int64_t nb, int T) {
-    const int64_t cnt = tri_count(nb) * (T / kUR) * kWaves;
+    const int64_t cnt = tri_count(nb) * units_per_tile(T) * kWaves;
     int64_t ns = cnt / (kVT * kBatch);
     ns = ns < 1 ? 1 : (ns > kSigSlices ? kSigSlices : ns);
     return ns + (n + kNPT - 1) / kNPT;
 }
 
-int units_per_tile(int T) { return T / kUR; }
 
 hipError_t launch_fill_u32(uint32_t* ptr, int64_t count, uint32_t value, hipStream_t s) {
     if (count <= 0) return hipSuccess;
@@ -839,11 +921,14 @@ int persistent_max_blocks_per_cu(int p, int latent, int T) {
 
 hipError_t launch_solve_persistent(const InstDesc* dd, int n_inst, const int64_t* d_unit_prefix,
                                    int64_t units_per_iter, int iters, int p, int latent, int T, int grid,
-                                   SolveCtl* ctl, uint32_t* epochs, int64_t spin_limit, hipStream_t s) {
+                                   SolveCtl* ctl, uint32_t* epochs, int64_t spin_limit, hipStream_t s,
+                                   LaunchTimer tm) {
     if (iters <= 0 || units_per_iter <= 0) return hipSuccess;
     const void* fn = persistent_ptr(p, latent, T);
     void* args[] = {(void*)&dd, (void*)&n_inst, (void*)&d_unit_prefix, (void*)&units_per_iter, (void*)&iters,
                     (void*)&ctl, (void*)&epochs, (void*)&spin_limit};
+    if (tm.start && tm.stop)
+        return hipExtLaunchKernel(fn, dim3((unsigned)grid), dim3(kWG), args, 0, s, tm.start, tm.stop, 0);
     return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kWG), args, 0, s);
 }
 

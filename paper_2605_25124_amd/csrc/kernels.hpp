@@ -37,6 +37,13 @@ struct InstDesc {
     float wtab[2 * kMaxP - 1];  // Gini latent: (p/2) W_{p,nu}[t], t = 2 .. 2p
 };
 
+// Optional events stamped by the runtime at the start and the end of one
+// kernel (profiling); both null for a plain launch.
+struct LaunchTimer {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+};
+
 // What a stress launch produces once every tile of an instance is done.
 enum StressMode : int {
     kModeGrad = 0,      // gradZ (scaled by *grad_out) and out_sigma
@@ -72,19 +79,20 @@ hipError_t launch_dissim(const DissimArgs& a, hipStream_t s);
 // Stream global work units q_base .. q_base+count-1 of the n_inst instances
 // described by `dd` (device; sorted by tile_off): tile partials only.
 hipError_t launch_stress_units(const InstDesc* dd, int n_inst, int64_t count, int64_t q_base, int p, int latent, int T,
-                               bool grad, hipStream_t s);
+                               bool grad, hipStream_t s, LaunchTimer tm = {});
 // Reduce the partials of every instance; `blocks` is the sum over instances
 // of reduce_block_count (instances sorted by red_off); blocks are numbered
 // from q_base.  StressMode says what
 // is produced; `it` indexes sigma_hist in descent mode.
 hipError_t launch_stress_reduce(const InstDesc* dd, int n_inst, int64_t blocks, int64_t q_base, int p, int latent,
-                                int T, int mode, int it, hipStream_t s);
+                                int T, int mode, int it, hipStream_t s, LaunchTimer tm = {});
 int64_t reduce_block_count(int64_t n, int64_t nb, int T);
 int units_per_tile(int T);
 // One launch: all instances, all iterations of the descent.
 hipError_t launch_solve_persistent(const InstDesc* dd, int n_inst, const int64_t* d_unit_prefix,
                                    int64_t units_per_iter, int iters, int p, int latent, int T, int grid,
-                                   SolveCtl* ctl, uint32_t* epochs, int64_t spin_limit, hipStream_t s);
+                                   SolveCtl* ctl, uint32_t* epochs, int64_t spin_limit, hipStream_t s,
+                                   LaunchTimer tm = {});
 int persistent_max_blocks_per_cu(int p, int latent, int T);
 // Set `count` words to `value` (counters, epochs).
 hipError_t launch_fill_u32(uint32_t* ptr, int64_t count, uint32_t value, hipStream_t s);

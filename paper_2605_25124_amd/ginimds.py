@@ -180,14 +180,17 @@ def gini_rank(V: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tens
 
 
 def padded_ld(n: int) -> int:
-    """Leading dimension for an n x n dissimilarity matrix: rows start on 16 bytes."""
-    return (n + 3) // 4 * 4
+    """Leading dimension for an n x n dissimilarity matrix: rows start on 256
+    bytes, so a tile row never straddles a cache line shared with the next
+    tile (with only 16-byte alignment half the rows of an n = 10000 matrix
+    would cost one extra 128-byte line per tile row)."""
+    return (n + 63) // 64 * 64
 
 
 def gini_dissim(X: torch.Tensor, nus: Sequence[float], out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Generalised Gini pseudo-distances of all pairs of rows of X for each nu.
 
-    Returns a (len(nus), n, n) view (rows padded to a multiple of 4 floats)."""
+    Returns a (len(nus), n, n) view (rows padded to a multiple of 64 floats)."""
     dev = _dev_index(X)
     ldx = _mat(X, "X")
     n, m = X.shape
