@@ -232,6 +232,41 @@ gini_status gini_mds_solve(gini_ctx* ctx, const gini_instance* inst, int32_t n_i
 gini_status gini_autotune(gini_ctx* ctx, const gini_instance* inst, int32_t n_inst,
                           int32_t probe_iters, gini_solve_opts* best, gini_stream_t stream);
 
+/* Options of gini_select_nu. */
+typedef struct {
+    int32_t iters;         /* descent steps of every (nu, fold) fit, >= 1    */
+    int32_t p;             /* latent dimension, as in gini_instance          */
+    gini_latent latent;    /* latent distance of the fit (GINI: Section IV-B) */
+    int32_t folds;         /* K >= 1; fold f holds rows [f*n/K, (f+1)*n/K)   */
+    int32_t flags;         /* launch mode, as gini_solve_opts.flags          */
+    int32_t tile;          /* 0 = library choice, else 64, 128 or 256        */
+} gini_select_opts;
+
+/*
+ * gini_select_nu -- Algorithm 1 (optimised Gini MDS) in one call.  For every
+ * nu of the list and every fold: the Gini dissimilarities of the fold's rows
+ * (gini_dissim; one ranking per pair serves every nu), `iters` descent steps
+ * from the fold's rows of Z0 (gini_mds_solve, all nu x folds fits batched
+ * together), then the Kruskal stress of the fitted configuration with the
+ * Euclidean latent distance, the statistic Algorithm 1 compares:
+ *     KS = sqrt( sum_{i<j} (|Z_i - Z_j|_2 - Delta_ij)^2 / sum_{i<j} Delta_ij^2 ).
+ * The mean KS over the folds picks nu* = argmin (the first on ties).
+ * X: n x m FP32 (ldx >= m), 1 <= m <= 4096.  nu: HOST array of n_nu values
+ * (1 <= n_nu <= 64), each finite and > 1.  Z0: n x p FP32 (ldz0 >= p).
+ * Z_out: n_nu configurations n x p (ldzo >= p), configuration k at
+ * Z_out + k*stride_z (stride_z >= n*ldzo when n_nu > 1); the rows of fold f
+ * are fitted against fold f only.  ks_mean: HOST double[n_nu]; ks_fold: HOST
+ * double[n_nu*folds] (nu-major) or NULL; best: HOST int32, the index of nu*.
+ * Every fold needs at least two rows (n >= 2*folds).  The dissimilarities
+ * live in a context-owned device workspace of
+ * sum_f n_nu * n_f * ceil64(n_f) floats, grown on demand.  Synchronises
+ * `stream`.
+ */
+gini_status gini_select_nu(gini_ctx* ctx, const float* X, int64_t n, int32_t m, int64_t ldx, const double* nu,
+                           int32_t n_nu, const float* Z0, int64_t ldz0, const gini_select_opts* opts,
+                           float* Z_out, int64_t ldzo, int64_t stride_z, double* ks_mean, double* ks_fold,
+                           int32_t* best, gini_stream_t stream);
+
 /* Kernel timing collected by the context while profiling is enabled: HIP
  * events recorded on the launching stream around each stress-tile launch,
  * each reduction launch and each persistent launch. */

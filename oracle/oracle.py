@@ -163,6 +163,28 @@ def kruskal(Delta, Z, nu: float, latent: int = LATENT_GINI, mode: int = MATCH32)
     return float(np.sqrt(s / den)) if den > 0 else 0.0
 
 
+def select_nu(X, nus, Z0, iters: int, folds: int = 1, latent: int = LATENT_GINI, mode: int = MATCH32):
+    """Algorithm 1: for each nu and each fold (rows [f n / K, (f+1) n / K)),
+    the fold's dissimilarities, `iters` descent steps from the fold's rows of
+    Z0, and the Kruskal stress of the result with the Euclidean latent
+    distance; nu* minimises the mean over the folds.  Returns
+    (best index, ks_mean[n_nu], ks_fold[n_nu, folds], final Z per nu)."""
+    X = np.asarray(X)
+    Z0 = np.asarray(Z0)
+    n = X.shape[0]
+    ks = np.zeros((len(nus), folds))
+    Zs = np.zeros((len(nus),) + Z0.shape)
+    for k, nu in enumerate(nus):
+        for f in range(folds):
+            a, b = f * n // folds, (f + 1) * n // folds
+            D = dissim(X[a:b], [nu], mode)[0]
+            Z, _ = solve(D, Z0[a:b], nu, iters, latent, mode)
+            Zs[k, a:b] = Z
+            ks[k, f] = kruskal(D, Z, nu, LATENT_EUCLID, mode)
+    mean = ks.mean(axis=1)
+    return int(np.argmin(mean)), mean, ks, Zs
+
+
 def grad_rows(Drows, rows, Z, nu: float, latent: int = LATENT_GINI, mode: int = MATCH32):
     """Gradient rows G[rows] from the corresponding rows of Delta; also returns
     the partial sum over the selected rows of sum_{j>i} r_ij^2."""

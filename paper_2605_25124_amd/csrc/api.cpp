@@ -77,6 +77,9 @@ struct gini_ctx {
     std::vector<hipEvent_t> ev_pool;
     int64_t spin_limit = 1000000000;   // ticks of the constant-rate device clock
     bool spin_override = false;
+    // gini_select_nu: the folds' dissimilarities and the small result buffers
+    float* sel = nullptr;
+    size_t sel_bytes = 0;
 };
 
 namespace {
@@ -220,6 +223,19 @@ gini_status ensure_scratch(gini_ctx* c, size_t bytes) {
     if (hipMalloc(reinterpret_cast<void**>(&c->scratch), cap) != hipSuccess)
         return fail(c, GINI_ENOMEM, "scratch allocation of %zu bytes failed", cap);
     c->scratch_bytes = cap;
+    return GINI_OK;
+}
+
+gini_status ensure_select(gini_ctx* c, size_t bytes) {
+    if (bytes <= c->sel_bytes) return GINI_OK;
+    if (c->sel) {
+        GINI_HIP(c, hipFree(c->sel));
+        c->sel = nullptr;
+        c->sel_bytes = 0;
+    }
+    if (hipMalloc(reinterpret_cast<void**>(&c->sel), bytes) != hipSuccess)
+        return fail(c, GINI_ENOMEM, "select workspace of %zu bytes failed", bytes);
+    c->sel_bytes = bytes;
     return GINI_OK;
 }
 
@@ -782,6 +798,7 @@ void gini_destroy(gini_ctx* c) {
             (void)hipFree(c->epochs);
         }
         if (c->cnt) (void)hipFree(c->cnt);
+        if (c->sel) (void)hipFree(c->sel);
         prof_clear(c);
         for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
         for (auto& sl : c->ring) {
@@ -970,6 +987,148 @@ gini_status gini_autotune(gini_ctx* c, const gini_instance* inst, int32_t n_inst
     st = autotune_impl(c, inst, n_inst, probe_iters, best, reinterpret_cast<hipStream_t>(stream));
     if (st == GINI_OK) best->flags |= keep;
     return st;
+}
+
+// Raw stress of every instance (no gradient) into out_sigma[2k], [2k+1]:
+// one stress-tile launch and one stress-only reduction for the whole batch.
+static gini_status eval_sigma_batch(gini_ctx* c, const gini_instance* inst, int n_inst, int T, float* out_sigma,
+                                    hipStream_t s) {
+    Plan P;
+    gini_status st = make_plan(c, inst, n_inst, T, P, s);
+    if (st != GINI_OK) return st;
+    for (int k = 0; k < n_inst; ++k) P.desc[k].out_sigma = out_sigma + 2 * P.order[k];
+    void* dd = nullptr;
+    Slot* sl = nullptr;
+    st = upload(c, P.desc.data(), P.desc.size() * sizeof(InstDesc), s, &dd, &sl);
+    if (st != GINI_OK) return st;
+    const InstDesc* ddp = static_cast<const InstDesc*>(dd);
+    {
+        ProfScope ps(c, kProfTile, s, true);
+        GINI_HIP(c, gmds::launch_stress_units(ddp, n_inst, P.tiles, 0, P.p, P.latent, T, false, s, ps.timer()));
+    }
+    {
+        ProfScope ps(c, kProfReduce, s, true);
+        GINI_HIP(c, gmds::launch_stress_reduce(ddp, n_inst, P.rblocks, 0, P.p, P.latent, T, gmds::kModeSigma, 0, s,
+                                               ps.timer()));
+    }
+    return slot_done(c, sl, s);
+}
+
+gini_status gini_select_nu(gini_ctx* c, const float* X, int64_t n, int32_t m, int64_t ldx, const double* nu,
+                           int32_t n_nu, const float* Z0, int64_t ldz0, const gini_select_opts* o, float* Z_out,
+                           int64_t ldzo, int64_t stride_z, double* ks_mean, double* ks_fold, int32_t* best,
+                           gini_stream_t stream) {
+    if (!c) return GINI_EINVAL;
+    c->err.clear();
+    if (!o) return fail(c, GINI_EINVAL, "opts must be non-null");
+    if (!X || !nu || !Z0 || !Z_out || !ks_mean || !best)
+        return fail(c, GINI_EINVAL, "X, nu, Z0, Z_out, ks_mean and best must be non-null");
+    if (m < 1 || m > kMaxDissimM) return fail(c, GINI_EINVAL, "m = %d outside 1..%d", m, kMaxDissimM);
+    if (ldx < m) return fail(c, GINI_EINVAL, "ldx = %lld < m = %d", (long long)ldx, m);
+    if (n_nu < 1 || n_nu > gmds::kMaxNu) return fail(c, GINI_EINVAL, "n_nu = %d outside 1..%d", n_nu, gmds::kMaxNu);
+    for (int k = 0; k < n_nu; ++k)
+        if (bad_nu(nu[k])) return fail(c, GINI_EINVAL, "nu[%d] must be finite and > 1", k);
+    if (o->folds < 1 || n < 2 * (int64_t)o->folds)
+        return fail(c, GINI_EINVAL, "folds = %d with n = %lld: every fold needs at least two rows", o->folds,
+                    (long long)n);
+    if (o->iters < 1) return fail(c, GINI_EINVAL, "iters = %d < 1", o->iters);
+    if ((int64_t)n_nu * o->folds > 65536) return fail(c, GINI_EINVAL, "n_nu * folds > 65536");
+    gini_status st = check_latent(c, o->p, nu[0], o->latent);
+    if (st != GINI_OK) return st;
+    const int p = o->p;
+    if (ldz0 < p || ldzo < p) return fail(c, GINI_EINVAL, "ldz0 and ldzo must be >= p = %d", p);
+    if (n_nu > 1 && stride_z < n * ldzo) return fail(c, GINI_EINVAL, "stride_z = %lld < n*ldzo", (long long)stride_z);
+    if (n > (int64_t)1 << 22) return fail(c, GINI_EUNSUPPORTED, "n > 2^22 is not supported");
+    gini_solve_opts so{o->iters, o->flags, o->tile, 0};
+    st = check_opts(c, &so);
+    if (st != GINI_OK) return st;
+    st = ensure_ready(c);
+    if (st != GINI_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+
+    // workspace: per fold, n_nu stacked n_f x ld_f matrices (rows on 256 B);
+    // then the normalisers and the Euclidean stresses, (hi, lo) per fit
+    const int K = o->folds;
+    const int nfit = n_nu * K;
+    std::vector<int64_t> start(K + 1), ld(K);
+    std::vector<size_t> off(K);
+    size_t floats = 0;
+    for (int f = 0; f <= K; ++f) start[f] = (int64_t)f * n / K;
+    for (int f = 0; f < K; ++f) {
+        const int64_t nf = start[f + 1] - start[f];
+        ld[f] = (nf + 63) / 64 * 64;
+        off[f] = floats;
+        floats += (size_t)n_nu * nf * ld[f];
+        floats = (floats + 63) & ~size_t(63);
+    }
+    const size_t sumsq_off = floats;
+    const size_t sig_off = floats + 2 * (size_t)nfit;
+    floats += 4 * (size_t)nfit;
+    st = ensure_select(c, floats * sizeof(float));
+    if (st != GINI_OK) return st;
+    float* ws = c->sel;
+
+    // 1. dissimilarities of every fold for every nu (one ranking per pair),
+    //    and their normalisers
+    for (int f = 0; f < K; ++f) {
+        const int64_t nf = start[f + 1] - start[f];
+        float* Df = ws + off[f];
+        st = gini_dissim(c, X + start[f] * ldx, nf, m, ldx, nu, n_nu, Df, ld[f], nf * ld[f], stream);
+        if (st != GINI_OK) return st;
+        st = gini_sumsq(c, Df, nf, ld[f], n_nu, nf * ld[f], ws + sumsq_off + 2 * (size_t)f * n_nu, stream);
+        if (st != GINI_OK) return st;
+    }
+    // 2. every configuration starts from Z0
+    for (int k = 0; k < n_nu; ++k)
+        GINI_HIP(c, hipMemcpy2DAsync(Z_out + (size_t)k * stride_z, (size_t)ldzo * sizeof(float), Z0,
+                                     (size_t)ldz0 * sizeof(float), (size_t)p * sizeof(float), (size_t)n,
+                                     hipMemcpyDeviceToDevice, s));
+    // 3. all nu x folds fits in one batched descent
+    std::vector<gini_instance> inst(nfit);
+    int64_t maxn = 0;
+    for (int k = 0; k < n_nu; ++k)
+        for (int f = 0; f < K; ++f) {
+            const int64_t nf = start[f + 1] - start[f];
+            gini_instance& I = inst[k * K + f];
+            I = gini_instance{};
+            I.n = nf;
+            I.p = p;
+            I.Delta = ws + off[f] + (size_t)k * nf * ld[f];
+            I.ldd = ld[f];
+            I.Z = Z_out + (size_t)k * stride_z + (size_t)start[f] * ldzo;
+            I.ldz = ldzo;
+            I.nu = nu[k];
+            I.latent = o->latent;
+            maxn = std::max(maxn, nf);
+        }
+    st = solve_impl(c, inst.data(), nfit, &so, s);
+    if (st != GINI_OK) return st;
+    // 4. raw stress of every fit with the Euclidean latent distance
+    for (auto& I : inst) I.latent = GINI_LATENT_EUCLID;
+    st = eval_sigma_batch(c, inst.data(), nfit, pick_tile(maxn), ws + sig_off, s);
+    if (st != GINI_OK) return st;
+    // 5. KS per fit, mean over folds, argmin over nu
+    std::vector<float> h(4 * (size_t)nfit);
+    GINI_HIP(c, hipMemcpyAsync(h.data(), ws + sumsq_off, h.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    GINI_HIP(c, hipStreamSynchronize(s));
+    int bi = 0;
+    for (int k = 0; k < n_nu; ++k) {
+        double acc = 0.0;
+        for (int f = 0; f < K; ++f) {
+            const size_t q = (size_t)f * n_nu + k;                    // normaliser order: fold-major
+            const double den = (double)h[2 * q] + (double)h[2 * q + 1];
+            const size_t r = 2 * (size_t)nfit + 2 * ((size_t)k * K + f);
+            const double sig = (double)h[r] + (double)h[r + 1];
+            const double ks = den > 0.0 ? std::sqrt(sig / den) : 0.0;
+            if (ks_fold) ks_fold[(size_t)k * K + f] = ks;
+            acc += ks;
+        }
+        ks_mean[k] = acc / K;
+        if (!std::isfinite(ks_mean[k])) return fail(c, GINI_ENOTFINITE, "Kruskal stress of nu[%d] is not finite", k);
+        if (ks_mean[k] < ks_mean[bi]) bi = k;
+    }
+    *best = bi;
+    return GINI_OK;
 }
 
 }  // extern "C"

@@ -46,6 +46,11 @@ class _Instance(ctypes.Structure):
                 ("delta_sumsq", ctypes.c_void_p), ("ks_hist", ctypes.c_void_p)]
 
 
+class _SelectOpts(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("p", ctypes.c_int32), ("latent", ctypes.c_int),
+                ("folds", ctypes.c_int32), ("flags", ctypes.c_int32), ("tile", ctypes.c_int32)]
+
+
 class _Profile(ctypes.Structure):
     _fields_ = [("tile_launches", ctypes.c_int64), ("tile_ms", ctypes.c_double),
                 ("reduce_launches", ctypes.c_int64), ("reduce_ms", ctypes.c_double),
@@ -80,10 +85,12 @@ def _load():
     L.gini_stress_bwd.argtypes = [P, P, i64, i64, P, i32, i64, f64, ctypes.c_int, P, P, i64, P, P]
     L.gini_mds_solve.argtypes = [P, ctypes.POINTER(_Instance), i32, ctypes.POINTER(_Opts), P]
     L.gini_autotune.argtypes = [P, ctypes.POINTER(_Instance), i32, i32, ctypes.POINTER(_Opts), P]
+    L.gini_select_nu.argtypes = [P, P, i64, i32, i64, P, i32, P, i64, ctypes.POINTER(_SelectOpts), P, i64, i64,
+                                 P, P, P, P]
     L.gini_profile_enable.argtypes = [P, ctypes.c_int]
     L.gini_profile_read.argtypes = [P, ctypes.POINTER(_Profile)]
     for fn in ("gini_create", "gini_rank", "gini_dissim", "gini_sumsq", "gini_stress_fwd", "gini_stress_bwd",
-               "gini_mds_solve", "gini_autotune", "gini_profile_enable", "gini_profile_read"):
+               "gini_mds_solve", "gini_autotune", "gini_select_nu", "gini_profile_enable", "gini_profile_read"):
         getattr(L, fn).restype = ctypes.c_int
     return L
 
@@ -341,6 +348,43 @@ def gini_autotune(insts: Sequence[Instance], probe_iters: int = 3) -> dict:
     c = context(dev)
     c.check(_lib.gini_autotune(c.handle, arr, len(insts), int(probe_iters), ctypes.byref(best), _stream(dev)))
     return {"flags": int(best.flags), "tile": int(best.tile), "grid": int(best.grid)}
+
+
+def gini_select_nu(X: torch.Tensor, nus: Sequence[float], Z0: torch.Tensor, iters: int, folds: int = 1,
+                   latent: int = LATENT_GINI, flags: int = SOLVE_BATCHED, tile: int = 0,
+                   Z_out: Optional[torch.Tensor] = None):
+    """Algorithm 1: fit every nu on every fold, score each fit by its Kruskal
+    stress with the Euclidean latent distance, return nu* = argmin of the
+    fold mean.  Returns (best index, ks_mean[n_nu], ks_fold[n_nu, folds],
+    Z_out[n_nu, n, p]); synchronises the stream."""
+    import numpy as np
+    dev = _dev_index(X)
+    if _dev_index(Z0) != dev:
+        raise ValueError("X and Z0 must live on one device")
+    ldx = _mat(X, "X")
+    ldz0 = _mat(Z0, "Z0")
+    n, m = X.shape
+    if Z0.shape[0] != n:
+        raise ValueError("Z0 must have the rows of X")
+    p = int(Z0.shape[1])
+    k = len(nus)
+    if Z_out is None:
+        Z_out = torch.empty((k, n, p), dtype=torch.float32, device=X.device)
+    if Z_out.dim() != 3 or tuple(Z_out.shape) != (k, n, p) or Z_out.dtype != torch.float32:
+        raise ValueError("Z_out must be an FP32 tensor of shape (len(nus), n, p)")
+    if p > 1 and Z_out.stride(2) != 1:
+        raise ValueError("Z_out must have unit column stride")
+    ldzo = max(int(Z_out.stride(1)), p) if n > 1 else p
+    nus_h = (ctypes.c_double * k)(*[float(v) for v in nus])
+    ks_mean = np.zeros(k, dtype=np.float64)
+    ks_fold = np.zeros((k, int(folds)), dtype=np.float64)
+    best = ctypes.c_int32(-1)
+    opts = _SelectOpts(int(iters), p, int(latent), int(folds), int(flags), int(tile))
+    c = context(dev)
+    c.check(_lib.gini_select_nu(c.handle, _ptr(X), n, m, ldx, nus_h, k, _ptr(Z0), ldz0, ctypes.byref(opts),
+                                _ptr(Z_out), ldzo, int(Z_out.stride(0)), ctypes.c_void_p(ks_mean.ctypes.data),
+                                ctypes.c_void_p(ks_fold.ctypes.data), ctypes.byref(best), _stream(dev)))
+    return int(best.value), ks_mean, ks_fold, Z_out
 
 
 def gini_profile_enable(device: int = 0, enable: bool = True) -> None:

@@ -182,6 +182,32 @@ def test_sumsq_validation(gm):
     L.gini_destroy(h)
 
 
+def test_select_validation(gm):
+    L, h = gm._lib, _ctx(gm)
+    X, Z0, Zo = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    nu = (ctypes.c_double * 2)(2.0, 3.0)
+    bad = (ctypes.c_double * 2)(2.0, 0.5)
+    km = (ctypes.c_double * 2)()
+    best = ctypes.c_int32()
+
+    def run(n=100, m=4, nus=nu, n_nu=2, opts=None, Zout=Zo, stride=1000, ldz0=2):
+        o = opts or gm._SelectOpts(10, 2, 0, 2, gm.SOLVE_BATCHED, 0)
+        return L.gini_select_nu(h, X, n, m, m, nus, n_nu, Z0, ldz0, ctypes.byref(o), Zout, 2, stride, km, None,
+                                ctypes.byref(best), None)
+
+    assert run(nus=bad) == EINVAL and "nu[1]" in _err(gm, h)
+    assert run(opts=gm._SelectOpts(10, 2, 0, 60, gm.SOLVE_BATCHED, 0)) == EINVAL and "fold" in _err(gm, h)
+    assert run(opts=gm._SelectOpts(0, 2, 0, 2, gm.SOLVE_BATCHED, 0)) == EINVAL and "iters" in _err(gm, h)
+    assert run(opts=gm._SelectOpts(10, 1, 0, 2, gm.SOLVE_BATCHED, 0)) == EINVAL           # Gini latent, p = 1
+    assert run(opts=gm._SelectOpts(10, 2, 0, 2, gm.SOLVE_BATCHED | gm.SOLVE_PLAIN, 0)) == EINVAL
+    assert run(m=0) == EINVAL
+    assert run(n_nu=0) == EINVAL
+    assert run(Zout=None) == EINVAL
+    assert run(stride=10) == EINVAL and "stride_z" in _err(gm, h)
+    assert run(ldz0=1) == EINVAL
+    L.gini_destroy(h)
+
+
 @pytest.mark.parametrize("d", [1, 2, 3, 10, 64, 784])
 @pytest.mark.parametrize("nu", [1.1, 1.5, 2.0, 3.7])
 def test_weight_table_matches_oracle_gradient(gm, orc, d, nu):

@@ -13,6 +13,8 @@ import pytest
 from scipy.spatial.distance import pdist, squareform
 from scipy.stats import rankdata
 
+from paper_2605_25124_amd import synth
+
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 NUS = [1.1, 1.5, 2.0, 3.0, 3.7, 5.0]
 
@@ -346,3 +348,39 @@ def test_grad_rows_matches_full_gradient(orc):
     allrows = np.arange(35)
     _, tot = orc.grad_rows(D, allrows, Z, 2.0, orc.LATENT_GINI, orc.MATCH32)
     assert tot == pytest.approx(s, rel=1e-12)
+
+
+# ------------------------------------------------------ Algorithm 1 (nu*)
+def test_select_nu_one_dimensional_data_is_fitted_exactly(orc):
+    """Rows of two coordinates: at any nu the dissimilarity is a multiple of
+    |y_i - y_j|, y = x_1 - x_2 (the d = 2 weights are -w, 0, +w), so the data
+    embed exactly in one Euclidean dimension.  From a start in the right order
+    one Guttman step (the Euclidean descent step) reaches the embedding, and
+    Algorithm 1's Kruskal stress is 0 for every nu and every fold."""
+    g = np.random.Generator(np.random.PCG64(71))
+    X = g.standard_normal((40, 2))
+    Z0 = 0.5 * (X[:, :1] - X[:, 1:])
+    best, mean, ks, _ = orc.select_nu(X, [1.5, 2.0, 3.0], Z0, 1, folds=2, latent=orc.LATENT_EUCLID,
+                                      mode=orc.EXACT)
+    assert ks.shape == (3, 2)
+    assert np.all(ks < 1e-12), ks
+    # a start in the wrong order is not fitted by one step
+    _, mean2, _, _ = orc.select_nu(X, [2.0], Z0[::-1].copy(), 1, folds=1, latent=orc.LATENT_EUCLID,
+                                   mode=orc.EXACT)
+    assert mean2[0] > 1e-3
+
+
+def test_select_nu_scale_invariance_and_argmin(orc):
+    """Distances are 1-homogeneous and the step size does not depend on the
+    scale, so scaling X and Z0 together leaves every KS unchanged; nu* is the
+    argmin of the fold means."""
+    w = synth.workload_small()
+    X, Z0 = w.X[:60], w.Z0[0][:60].astype(np.float64)
+    nus = [1.5, 2.0, 3.0]
+    best, mean, ks, Z = orc.select_nu(X, nus, Z0, 20, folds=2, mode=orc.EXACT)
+    best2, mean2, ks2, Z2 = orc.select_nu(4.0 * X, nus, 4.0 * Z0, 20, folds=2, mode=orc.EXACT)
+    np.testing.assert_allclose(ks2, ks, rtol=1e-9)
+    np.testing.assert_allclose(Z2, 4.0 * Z, rtol=1e-9, atol=1e-12)
+    assert best == best2 == int(np.argmin(ks.mean(axis=1)))
+    np.testing.assert_allclose(mean, ks.mean(axis=1))
+    assert np.all(np.isfinite(ks) & (ks > 0))
