@@ -15,6 +15,8 @@ Printed as ONE JSON line:
   sweep            the nu-sweep workload (16 problems x 8 nu = 128 instances):
                    instance-iterations/s of the batched solve vs the plain
                    one-instance-per-launch path
+  select           Algorithm 1's nu selection (gini_select_nu) on the
+                   Gaussian-mixture workload, end to end
   cpu_baseline     the FP64 oracle's stress + gradient on a bounded sample
 """
 from __future__ import annotations
@@ -45,6 +47,7 @@ def parse():
     ap.add_argument("--plain-iters", type=int, default=40)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-select", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--mode", choices=["auto", "persistent", "batched"], default="auto")
     ap.add_argument("--tile", type=int, default=256)
@@ -233,6 +236,24 @@ def main():
                  "plain_iters": args.plain_iters, "dissim_build_s": round(sweep_build, 3)}
         log(f"sweep batched {batched_rate:.0f} it/s, plain {plain_rate:.0f} it/s, x{batched_rate / plain_rate:.2f}")
 
+    # ---- Algorithm 1 (nu selection) on the Gaussian-mixture workload
+    select = None
+    if not args.no_select:
+        wg = synth.workload_gmm()
+        Xg = torch.from_numpy(wg.X).to(dev)
+        Zg = torch.from_numpy(wg.Z0[0]).to(dev)
+        gm.gini_select_nu(Xg, wg.nus, Zg, 5)                   # warm the library (tables, workspace)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bi, ks_mean, _, _ = gm.gini_select_nu(Xg, wg.nus, Zg, wg.iters)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        select = {"workload": f"Gaussian mixture n={wg.X.shape[0]} m={wg.X.shape[1]}, nu in {wg.nus}, p=2 Gini "
+                              f"latent, {wg.iters} descent steps per nu, one fold",
+                  "seconds": round(ts, 4), "nu_star": wg.nus[bi],
+                  "ks_mean": [round(float(v), 6) for v in ks_mean]}
+        log(f"select: nu* = {wg.nus[bi]} in {ts * 1e3:.1f} ms, KS {select['ks_mean']}")
+
     # ---- CPU baseline: the oracle as it stands, bounded sample
     cpu = None
     if not args.no_cpu_baseline:
@@ -266,7 +287,7 @@ def main():
                       "parallelism": "single GPU"},
            "hbm_gbs_algorithmic": round(achieved, 1),
            "dissim_build_s": round(dissim_s, 4),
-           "roofline": roof, "sweep": sweep, "cpu_baseline": cpu}
+           "roofline": roof, "sweep": sweep, "select": select, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
 

@@ -60,6 +60,12 @@ typedef enum {
  * used by Algorithm 1 to evaluate the Kruskal stress. */
 typedef enum { GINI_LATENT_GINI = 0, GINI_LATENT_EUCLID = 1 } gini_latent;
 
+/* Loss minimised by the descent (Section IV-B lists both).  RAW: the raw
+ * stress sum_{i<j} (delta_ij - Delta_ij)^2, the SMACOF loss with unit weights.
+ * SAMMON: Sammon's stress sum_{i<j} (delta_ij - Delta_ij)^2 / Delta_ij divided
+ * by sum_{i<j} Delta_ij; a pair with Delta_ij = 0 carries no weight. */
+typedef enum { GINI_LOSS_RAW = 0, GINI_LOSS_SAMMON = 1 } gini_loss;
+
 typedef struct gini_ctx gini_ctx;
 
 /* Create a context bound to HIP device `device` (>= 0).  No HIP call is made
@@ -136,6 +142,14 @@ gini_status gini_sumsq(gini_ctx* ctx, const float* Delta, int64_t n, int64_t ldd
                        int64_t stride, float* out, gini_stream_t stream);
 
 /*
+ * gini_sum -- the normaliser of the Sammon stress (Section IV-B),
+ *     out[2k] + out[2k+1] = sum_{i<j} Delta_k[i, j],
+ * with the arguments, layout and ordering of gini_sumsq.
+ */
+gini_status gini_sum(gini_ctx* ctx, const float* Delta, int64_t n, int64_t ldd, int32_t n_mat, int64_t stride,
+                     float* out, gini_stream_t stream);
+
+/*
  * gini_stress_fwd -- raw stress of the configuration Z against Delta (the
  * SMACOF loss of Section IV-B with unit weights, pairs i < j):
  *     sigma = sum_{i<j} (delta(Z_i - Z_j) - Delta[i,j])^2
@@ -167,23 +181,58 @@ gini_status gini_stress_bwd(gini_ctx* ctx, const float* Delta, int64_t n, int64_
                             const float* grad_out, float* gradZ, int64_t ldg, float* out_sigma,
                             gini_stream_t stream);
 
+/*
+ * gini_sammon_fwd / gini_sammon_bwd -- as gini_stress_fwd / gini_stress_bwd
+ * for Sammon's stress (Section IV-B):
+ *     sigma = (1 / S) sum_{i<j} (delta_ij - Delta_ij)^2 / Delta_ij,
+ *     S = sum_{i<j} Delta_ij = delta_sum[0] + delta_sum[1] (device, gini_sum),
+ * pairs with Delta_ij = 0 carry no weight; the gradient holds the latent ranks
+ * fixed.  out_sigma receives sigma as (hi, lo).  1 / Delta_ij is the hardware
+ * reciprocal (1 ulp).
+ */
+gini_status gini_sammon_fwd(gini_ctx* ctx, const float* Delta, int64_t n, int64_t ldd, const float* delta_sum,
+                            const float* Z, int32_t p, int64_t ldz, double nu, gini_latent latent,
+                            float* out_sigma, gini_stream_t stream);
+gini_status gini_sammon_bwd(gini_ctx* ctx, const float* Delta, int64_t n, int64_t ldd, const float* delta_sum,
+                            const float* Z, int32_t p, int64_t ldz, double nu, gini_latent latent,
+                            const float* grad_out, float* gradZ, int64_t ldg, float* out_sigma,
+                            gini_stream_t stream);
+
+/*
+ * gini_sammon_step -- a fixed descent step for the Sammon stress under which
+ * it does not increase (Euclidean latent distance, or the p = 2 Gini one):
+ *     eta = S / (4 c max_i sum_{j != i, Delta_ij > 0} 1 / Delta_ij),
+ * S = sum_{i<j} Delta_ij and c = |d delta / d u|^2 at a tie-free u (as in
+ * gini_mds_solve's default step).  2 max_i sum_j w_ij bounds the largest
+ * eigenvalue of the weighted Laplacian (Gershgorin), w_ij = 1 / (S Delta_ij),
+ * so the step stays inside the quadratic that majorises the stress.  Reads
+ * both triangles of Delta (n x n FP32, ldd >= n).  *eta: host.  Synchronises
+ * `stream`.
+ */
+gini_status gini_sammon_step(gini_ctx* ctx, const float* Delta, int64_t n, int64_t ldd, int32_t p, double nu,
+                             gini_latent latent, double* eta, gini_stream_t stream);
+
 /* One MDS instance for gini_mds_solve (all pointers are device pointers). */
 typedef struct {
     int64_t n;             /* points, >= 2                                     */
     int32_t p;             /* latent dimension, 1..8 (>= 2 for GINI)           */
-    int32_t reserved0;     /* must be 0                                        */
+    int32_t loss;          /* gini_loss; RAW or SAMMON (shared by one call)   */
     const float* Delta;    /* n x n dissimilarities (upper triangle read)      */
     int64_t ldd;           /* >= n                                             */
     float* Z;              /* n x p configuration, updated in place            */
     int64_t ldz;           /* >= p                                             */
     double nu;             /* > 1, used by the GINI latent distance            */
     gini_latent latent;
-    float eta;             /* step; <= 0 selects 1 / (2 n c) (see below)       */
+    float eta;             /* step; <= 0 selects 1 / (2 n c) (see below); the
+                              SAMMON loss needs eta > 0 (gini_sammon_step)    */
     float* sigma_hist;     /* iters floats: sigma(Z_t) before step t; or NULL  */
     const float* delta_sumsq; /* (hi, lo) from gini_sumsq of this Delta, or
                                  NULL; needed only by ks_hist                 */
     float* ks_hist;        /* iters floats: Kruskal stress
-                              sqrt(sigma(Z_t) / sum_{i<j} Delta_ij^2); or NULL */
+                              sqrt(sigma(Z_t) / sum_{i<j} Delta_ij^2); or NULL
+                              (RAW loss only)                                 */
+    const float* delta_sum;   /* (hi, lo) from gini_sum of this Delta; needed
+                                 by the SAMMON loss, else ignored              */
 } gini_instance;
 
 enum {

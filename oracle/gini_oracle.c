@@ -343,3 +343,81 @@ void orc_solve(const double* Delta, int64_t n, int64_t ldd, double* Z, int p, in
     }
     free(G);
 }
+
+/* Section IV-B, Sammon's stress: with S = sum_{i<j} Delta_ij,
+ *     (1/S) sum_{i<j} (delta_ij - Delta_ij)^2 / Delta_ij,
+ * a pair with Delta_ij = 0 carrying no weight (its weight is undefined), and
+ * its gradient with the latent ranks fixed. */
+double orc_sammon(const double* Delta, int64_t n, int64_t ldd, const double* Z, int p, int64_t ldz, double nu,
+                  int latent, int mode, double* G, int64_t ldg) {
+    orc_gini_ws w;
+    orc_ws_init(&w, p, nu);
+    double* u = (double*)malloc(sizeof(double) * (size_t)p);
+    double* a = (double*)malloc(sizeof(double) * (size_t)p);
+    double S = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = i + 1; j < n; ++j) S += Delta[i * ldd + j];
+    if (G)
+        for (int64_t i = 0; i < n; ++i)
+            for (int c = 0; c < p; ++c) G[i * ldg + c] = 0.0;
+    double sigma = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = i + 1; j < n; ++j) {
+            const double d = Delta[i * ldd + j];
+            if (!(d > 0.0)) continue;
+            for (int c = 0; c < p; ++c) u[c] = orc_diff(Z[i * ldz + c], Z[j * ldz + c], mode);
+            double delta = orc_latent(u, p, latent, &w, a);
+            double r = delta - d;
+            sigma += r * r / d;
+            if (G) {
+                for (int c = 0; c < p; ++c) {
+                    G[i * ldg + c] += 2.0 * r / d * a[c];
+                    G[j * ldg + c] -= 2.0 * r / d * a[c];
+                }
+            }
+        }
+    }
+    if (G)
+        for (int64_t i = 0; i < n; ++i)
+            for (int c = 0; c < p; ++c) G[i * ldg + c] = S > 0.0 ? G[i * ldg + c] / S : 0.0;
+    free(u); free(a);
+    orc_ws_free(&w);
+    return S > 0.0 ? sigma / S : 0.0;
+}
+
+/* A fixed step for the Sammon stress, 1 / (4 c max_i sum_{j != i} w_ij) with
+ * w_ij = 1 / (S Delta_ij) and c as in orc_step_size: the weighted Laplacian's
+ * largest eigenvalue is at most 2 max_i sum_j w_ij (Gershgorin), so the step
+ * never leaves the majorising quadratic and the stress does not increase
+ * (Euclidean latent distance, or the p = 2 Gini one). */
+double orc_sammon_step(const double* Delta, int64_t n, int64_t ldd, int p, double nu, int latent) {
+    double S = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = i + 1; j < n; ++j) S += Delta[i * ldd + j];
+    double mx = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double r = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double d = (j > i) ? Delta[i * ldd + j] : Delta[j * ldd + i];
+            if (j != i && d > 0.0) r += 1.0 / d;
+        }
+        if (r > mx) mx = r;
+    }
+    const double c = 1.0 / (2.0 * (double)n * orc_step_size(n, p, nu, latent));
+    return (mx > 0.0) ? S / (4.0 * c * mx) : 0.0;
+}
+
+/* Fixed-step descent on the Sammon stress; eta <= 0 selects orc_sammon_step. */
+void orc_solve_sammon(const double* Delta, int64_t n, int64_t ldd, double* Z, int p, int64_t ldz, double nu,
+                      int latent, int mode, int iters, double eta, double* sigma_hist) {
+    if (eta <= 0.0) eta = orc_sammon_step(Delta, n, ldd, p, nu, latent);
+    double* G = (double*)malloc(sizeof(double) * (size_t)(n * p));
+    for (int it = 0; it < iters; ++it) {
+        double s = orc_sammon(Delta, n, ldd, Z, p, ldz, nu, latent, mode, G, p);
+        if (sigma_hist) sigma_hist[it] = s;
+        for (int64_t i = 0; i < n; ++i)
+            for (int c = 0; c < p; ++c) Z[i * ldz + c] -= eta * G[i * p + c];
+    }
+    free(G);
+}
+

@@ -69,6 +69,11 @@ def lib():
         L.orc_step_size.argtypes = [i64, i32, f64, i32]
         L.orc_step_size.restype = f64
         L.orc_solve.argtypes = [P, i64, i64, P, i32, i64, f64, i32, i32, i32, f64, P]
+        L.orc_sammon.argtypes = [P, i64, i64, P, i32, i64, f64, i32, i32, P, i64]
+        L.orc_sammon.restype = f64
+        L.orc_sammon_step.argtypes = [P, i64, i64, i32, f64, i32]
+        L.orc_sammon_step.restype = f64
+        L.orc_solve_sammon.argtypes = [P, i64, i64, P, i32, i64, f64, i32, i32, i32, f64, P]
         _lib = L
     return _lib
 
@@ -161,6 +166,34 @@ def kruskal(Delta, Z, nu: float, latent: int = LATENT_GINI, mode: int = MATCH32)
     s, _ = stress(Delta, Z, nu, latent, mode, grad=False)
     den = delta_sumsq(Delta)
     return float(np.sqrt(s / den)) if den > 0 else 0.0
+
+
+def sammon(Delta, Z, nu: float, latent: int = LATENT_GINI, mode: int = MATCH32, grad: bool = True):
+    """(sigma, G): Sammon's stress (1/S) sum_{i<j} (delta_ij - Delta_ij)^2 / Delta_ij, S = sum Delta_ij."""
+    D = _f64(Delta)
+    Z = _f64(Z)
+    n, p = Z.shape
+    G = np.empty((n, p), dtype=np.float64) if grad else None
+    s = lib().orc_sammon(_ptr(D), n, D.shape[1], _ptr(Z), p, p, float(nu), latent, mode,
+                         _ptr(G) if grad else None, p)
+    return float(s), G
+
+
+def sammon_step(Delta, p: int, nu: float, latent: int = LATENT_GINI) -> float:
+    D = _f64(Delta)
+    return float(lib().orc_sammon_step(_ptr(D), D.shape[0], D.shape[1], p, float(nu), latent))
+
+
+def solve_sammon(Delta, Z0, nu: float, iters: int, latent: int = LATENT_GINI, mode: int = MATCH32,
+                 eta: float = 0.0):
+    """Fixed-step descent on the Sammon stress; returns (Z_T, sigma history)."""
+    D = _f64(Delta)
+    Z = _f64(Z0).copy()
+    n, p = Z.shape
+    hist = np.empty(iters, dtype=np.float64)
+    lib().orc_solve_sammon(_ptr(D), n, D.shape[1], _ptr(Z), p, p, float(nu), latent, mode, iters,
+                           float(eta), _ptr(hist))
+    return Z, hist
 
 
 def select_nu(X, nus, Z0, iters: int, folds: int = 1, latent: int = LATENT_GINI, mode: int = MATCH32):

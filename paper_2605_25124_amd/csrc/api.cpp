@@ -376,9 +376,10 @@ void assign_partials(InstDesc& D, float* base, int T, int pg) {
 
 gini_status stress_common(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, const float* Z, int32_t p,
                           int64_t ldz, double nu, gini_latent latent, const float* grad_out, float* gradZ,
-                          int64_t ldg, float* out_sigma, bool grad, hipStream_t s) {
+                          int64_t ldg, float* out_sigma, bool grad, int loss, const float* dsum, hipStream_t s) {
     if (!c) return GINI_EINVAL;
     c->err.clear();
+    if (loss == GINI_LOSS_SAMMON && !dsum) return fail(c, GINI_EINVAL, "delta_sum must be non-null");
     if (!Delta || !Z) return fail(c, GINI_EINVAL, "Delta and Z must be non-null");
     if (n < 2) return fail(c, GINI_EINVAL, "n = %lld: need at least two points", (long long)n);
     if (ldd < n) return fail(c, GINI_EINVAL, "ldd = %lld < n = %lld", (long long)ldd, (long long)n);
@@ -401,6 +402,8 @@ gini_status stress_common(gini_ctx* c, const float* Delta, int64_t n, int64_t ld
     D.gradZ = gradZ;
     D.grad_out = grad_out;
     D.out_sigma = out_sigma;
+    D.loss = loss;
+    D.dsum = dsum;
     D.n = n;
     D.ldd = ldd;
     D.ldz = ldz;
@@ -427,7 +430,7 @@ gini_status stress_common(gini_ctx* c, const float* Delta, int64_t n, int64_t ld
     const InstDesc* ddp = static_cast<const InstDesc*>(dd);
     {
         ProfScope ps(c, kProfTile, s, true);
-        GINI_HIP(c, gmds::launch_stress_units(ddp, 1, nt, 0, p, latent, T, grad, s, ps.timer()));
+        GINI_HIP(c, gmds::launch_stress_units(ddp, 1, nt, 0, p, latent, T, grad, loss, s, ps.timer()));
     }
     {
         ProfScope ps(c, kProfReduce, s, true);
@@ -444,7 +447,7 @@ struct Plan {
     std::vector<int64_t> prefix;    // work-unit prefix, n_inst + 1
     int64_t tiles = 0;              // work units per iteration
     int64_t rblocks = 0;            // reduction blocks per iteration
-    int p = 0, latent = 0, T = 0;
+    int p = 0, latent = 0, T = 0, loss = 0;
 };
 
 gini_status validate_instances(gini_ctx* c, const gini_instance* inst, int32_t n_inst) {
@@ -457,14 +460,22 @@ gini_status validate_instances(gini_ctx* c, const gini_instance* inst, int32_t n
         if ((uint64_t)I.n > (uint64_t)1 << 31) return fail(c, GINI_EUNSUPPORTED, "instance %d: n too large", k);
         if (I.ldd < I.n) return fail(c, GINI_EINVAL, "instance %d: ldd < n", k);
         if (I.ldz < I.p) return fail(c, GINI_EINVAL, "instance %d: ldz < p", k);
-        if (I.reserved0 != 0) return fail(c, GINI_EINVAL, "instance %d: reserved0 must be 0", k);
+        if (I.loss != GINI_LOSS_RAW && I.loss != GINI_LOSS_SAMMON)
+            return fail(c, GINI_EINVAL, "instance %d: unknown loss %d", k, (int)I.loss);
+        if (I.loss == GINI_LOSS_SAMMON && !I.delta_sum)
+            return fail(c, GINI_EINVAL, "instance %d: the Sammon loss needs delta_sum", k);
+        if (I.loss == GINI_LOSS_SAMMON && !(I.eta > 0.f))
+            return fail(c, GINI_EINVAL, "instance %d: the Sammon loss needs eta > 0 (see gini_sammon_step)", k);
+        if (I.loss == GINI_LOSS_SAMMON && I.ks_hist)
+            return fail(c, GINI_EINVAL, "instance %d: ks_hist is defined for the raw stress only", k);
         if (!std::isfinite(I.eta)) return fail(c, GINI_EINVAL, "instance %d: eta not finite", k);
         if (I.ks_hist && !I.delta_sumsq)
             return fail(c, GINI_EINVAL, "instance %d: ks_hist needs delta_sumsq", k);
         gini_status st = check_latent(c, I.p, I.nu, I.latent);
         if (st != GINI_OK) return fail(c, st, "instance %d: %s", k, c->err.c_str());
-        if (I.p != inst[0].p || I.latent != inst[0].latent)
-            return fail(c, GINI_EUNSUPPORTED, "instance %d: all instances of one call must share p and latent", k);
+        if (I.p != inst[0].p || I.latent != inst[0].latent || I.loss != inst[0].loss)
+            return fail(c, GINI_EUNSUPPORTED, "instance %d: all instances of one call must share p, latent and loss",
+                        k);
     }
     for (int k = 0; k < n_inst; ++k)
         for (int l = k + 1; l < n_inst && n_inst <= 4096; ++l) {
@@ -480,6 +491,7 @@ gini_status validate_instances(gini_ctx* c, const gini_instance* inst, int32_t n
 gini_status make_plan(gini_ctx* c, const gini_instance* inst, int32_t n_inst, int T, Plan& P, hipStream_t s) {
     P.p = inst[0].p;
     P.latent = inst[0].latent;
+    P.loss = inst[0].loss;
     P.T = T;
     P.order.resize(n_inst);
     std::iota(P.order.begin(), P.order.end(), 0);
@@ -498,6 +510,8 @@ gini_status make_plan(gini_ctx* c, const gini_instance* inst, int32_t n_inst, in
         D.sigma_hist = I.sigma_hist;
         D.dsumsq = I.delta_sumsq;
         D.ks_hist = I.ks_hist;
+        D.dsum = I.delta_sum;
+        D.loss = I.loss;
         D.n = I.n;
         D.ldd = I.ldd;
         D.ldz = I.ldz;
@@ -566,7 +580,7 @@ gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStr
                 {
                     ProfScope ps(c, kProfTile, s, true);
                     GINI_HIP(c, gmds::launch_stress_units(ddp + k, 1, nu, P.desc[k].tile_off, P.p, P.latent, P.T,
-                                                          true, s, ps.timer()));
+                                                          true, P.loss, s, ps.timer()));
                 }
                 ProfScope ps(c, kProfReduce, s, true);
                 GINI_HIP(c, gmds::launch_stress_reduce(ddp + k, 1,
@@ -579,7 +593,7 @@ gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStr
         for (int it = 0; it < iters; ++it) {
             {
                 ProfScope ps(c, kProfTile, s, true);
-                GINI_HIP(c, gmds::launch_stress_units(ddp, n_inst, P.tiles, 0, P.p, P.latent, P.T, true, s,
+                GINI_HIP(c, gmds::launch_stress_units(ddp, n_inst, P.tiles, 0, P.p, P.latent, P.T, true, P.loss, s,
                                                       ps.timer()));
             }
             ProfScope ps(c, kProfReduce, s, true);
@@ -590,11 +604,11 @@ gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStr
         hipLaunchKernelGGL(k_reset_ctl, dim3((n_inst + 255) / 256), dim3(256), 0, s, c->ctl, c->epochs, n_inst);
         GINI_HIP(c, hipGetLastError());
         int g = grid;
-        if (g <= 0) g = c->cus * gmds::persistent_max_blocks_per_cu(P.p, P.latent, P.T);
+        if (g <= 0) g = c->cus * gmds::persistent_max_blocks_per_cu(P.p, P.latent, P.T, P.loss);
         const int64_t cap = P.tiles * (int64_t)iters;
         if (g > cap) g = (int)std::max<int64_t>(1, cap);
         ProfScope ps(c, kProfPersistent, s, true);
-        GINI_HIP(c, gmds::launch_solve_persistent(ddp, n_inst, dprefix, P.tiles, iters, P.p, P.latent, P.T, g,
+        GINI_HIP(c, gmds::launch_solve_persistent(ddp, n_inst, dprefix, P.tiles, iters, P.p, P.latent, P.T, P.loss, g,
                                                   c->ctl, c->epochs, c->spin_limit, s, ps.timer()));
     }
     if (ev1) GINI_HIP(c, hipEventRecord(ev1, s));
@@ -665,7 +679,7 @@ gini_status autotune_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst
     for (int T : {64, 128, 256}) {
         if (T > 64 && maxn <= T / 2) continue;
         cand.push_back({probe_iters, GINI_SOLVE_BATCHED, T, 0});
-        int nb = gmds::persistent_max_blocks_per_cu(inst[0].p, inst[0].latent, T);
+        int nb = gmds::persistent_max_blocks_per_cu(inst[0].p, inst[0].latent, T, inst[0].loss);
         for (int g : {1, 2, 4, 8}) {
             if (g > nb) break;
             cand.push_back({probe_iters, GINI_SOLVE_PERSISTENT, T, g * c->cus});
@@ -887,8 +901,8 @@ gini_status gini_dissim(gini_ctx* c, const float* X, int64_t n, int32_t m, int64
     return GINI_OK;
 }
 
-gini_status gini_sumsq(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, int32_t n_mat, int64_t stride,
-                       float* out, gini_stream_t stream) {
+static gini_status sum_common(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, int32_t n_mat,
+                              int64_t stride, float* out, int power, gini_stream_t stream) {
     if (!c) return GINI_EINVAL;
     c->err.clear();
     if (!Delta || !out) return fail(c, GINI_EINVAL, "Delta and out must be non-null");
@@ -902,21 +916,77 @@ gini_status gini_sumsq(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     st = ensure_scratch(c, (size_t)2 * n_mat * std::max<int64_t>(1, gmds::sumsq_blocks(n)) * sizeof(float));
     if (st != GINI_OK) return st;
-    GINI_HIP(c, gmds::launch_sumsq(Delta, n, ldd, n_mat, n_mat > 1 ? stride : 0, c->scratch, out, s));
+    GINI_HIP(c, gmds::launch_sumsq(Delta, n, ldd, n_mat, n_mat > 1 ? stride : 0, c->scratch, out, power, s));
+    return GINI_OK;
+}
+
+gini_status gini_sumsq(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, int32_t n_mat, int64_t stride,
+                       float* out, gini_stream_t stream) {
+    return sum_common(c, Delta, n, ldd, n_mat, stride, out, 2, stream);
+}
+
+gini_status gini_sum(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, int32_t n_mat, int64_t stride,
+                     float* out, gini_stream_t stream) {
+    return sum_common(c, Delta, n, ldd, n_mat, stride, out, 1, stream);
+}
+
+gini_status gini_sammon_step(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, int32_t p, double nu,
+                             gini_latent latent, double* eta, gini_stream_t stream) {
+    if (!c) return GINI_EINVAL;
+    c->err.clear();
+    if (!Delta || !eta) return fail(c, GINI_EINVAL, "Delta and eta must be non-null");
+    if (n < 2) return fail(c, GINI_EINVAL, "n = %lld: need at least two points", (long long)n);
+    if (ldd < n) return fail(c, GINI_EINVAL, "ldd = %lld < n = %lld", (long long)ldd, (long long)n);
+    gini_status st = check_latent(c, p, nu, latent);
+    if (st != GINI_OK) return st;
+    if (n > (int64_t)1 << 31) return fail(c, GINI_EUNSUPPORTED, "n too large");
+    st = ensure_ready(c);
+    if (st != GINI_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // scratch: [sum hi, lo][max row sum][pad][sum partials][row-max partials]
+    const size_t sq = (size_t)2 * std::max<int64_t>(1, gmds::sumsq_blocks(n));
+    const size_t rb = (size_t)gmds::rowinv_blocks(n);
+    st = ensure_scratch(c, (4 + sq + rb) * sizeof(float));
+    if (st != GINI_OK) return st;
+    float* out = c->scratch;
+    GINI_HIP(c, gmds::launch_sumsq(Delta, n, ldd, 1, 0, c->scratch + 4, out, 1, s));
+    GINI_HIP(c, gmds::launch_rowinv_max(Delta, n, ldd, c->scratch + 4 + sq, out + 2, s));
+    float h[3];
+    GINI_HIP(c, hipMemcpyAsync(h, out, sizeof h, hipMemcpyDeviceToHost, s));
+    GINI_HIP(c, hipStreamSynchronize(s));
+    InstDesc D{};
+    double cc;
+    latent_consts(p, nu, latent, D, cc);
+    const double S = (double)h[0] + (double)h[1];
+    *eta = (h[2] > 0.f && cc > 0.0) ? S / (4.0 * cc * (double)h[2]) : 0.0;
     return GINI_OK;
 }
 
 gini_status gini_stress_fwd(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, const float* Z, int32_t p,
                             int64_t ldz, double nu, gini_latent latent, float* out_sigma, gini_stream_t stream) {
     return stress_common(c, Delta, n, ldd, Z, p, ldz, nu, latent, nullptr, nullptr, p, out_sigma, false,
-                         reinterpret_cast<hipStream_t>(stream));
+                         GINI_LOSS_RAW, nullptr, reinterpret_cast<hipStream_t>(stream));
 }
 
 gini_status gini_stress_bwd(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, const float* Z, int32_t p,
                             int64_t ldz, double nu, gini_latent latent, const float* grad_out, float* gradZ,
                             int64_t ldg, float* out_sigma, gini_stream_t stream) {
     return stress_common(c, Delta, n, ldd, Z, p, ldz, nu, latent, grad_out, gradZ, ldg, out_sigma, true,
-                         reinterpret_cast<hipStream_t>(stream));
+                         GINI_LOSS_RAW, nullptr, reinterpret_cast<hipStream_t>(stream));
+}
+
+gini_status gini_sammon_fwd(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, const float* delta_sum,
+                            const float* Z, int32_t p, int64_t ldz, double nu, gini_latent latent, float* out_sigma,
+                            gini_stream_t stream) {
+    return stress_common(c, Delta, n, ldd, Z, p, ldz, nu, latent, nullptr, nullptr, p, out_sigma, false,
+                         GINI_LOSS_SAMMON, delta_sum, reinterpret_cast<hipStream_t>(stream));
+}
+
+gini_status gini_sammon_bwd(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, const float* delta_sum,
+                            const float* Z, int32_t p, int64_t ldz, double nu, gini_latent latent,
+                            const float* grad_out, float* gradZ, int64_t ldg, float* out_sigma, gini_stream_t stream) {
+    return stress_common(c, Delta, n, ldd, Z, p, ldz, nu, latent, grad_out, gradZ, ldg, out_sigma, true,
+                         GINI_LOSS_SAMMON, delta_sum, reinterpret_cast<hipStream_t>(stream));
 }
 
 gini_status gini_mds_solve(gini_ctx* c, const gini_instance* inst, int32_t n_inst, const gini_solve_opts* opts,
@@ -1004,7 +1074,8 @@ static gini_status eval_sigma_batch(gini_ctx* c, const gini_instance* inst, int 
     const InstDesc* ddp = static_cast<const InstDesc*>(dd);
     {
         ProfScope ps(c, kProfTile, s, true);
-        GINI_HIP(c, gmds::launch_stress_units(ddp, n_inst, P.tiles, 0, P.p, P.latent, T, false, s, ps.timer()));
+        GINI_HIP(c, gmds::launch_stress_units(ddp, n_inst, P.tiles, 0, P.p, P.latent, T, false, P.loss, s,
+                                              ps.timer()));
     }
     {
         ProfScope ps(c, kProfReduce, s, true);

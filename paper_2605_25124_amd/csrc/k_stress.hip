@@ -1,822 +1,13 @@
-// k_stress.hip -- fused raw-stress forward + backward over the upper triangle of
-// Delta, the deterministic reduction of its partial sums, and the persistent
-// multi-instance solver.
-//
-// Work decomposition.  The strict upper triangle {i < j} of an n x n problem is
-// cut into T x T tiles (I, J), I <= J, enumerated row by row (tri_index), and
-// every tile into T/UR work units of UR consecutive rows.  One 256-thread
-// workgroup streams one unit of Delta exactly once.  Sixteen lanes (one DPP
-// row) cover a tile row: lane c4 owns the columns 4*(c4 + 16q) .. +3, q < T/64,
-// read as 16-byte global loads, so each load instruction fetches 256 contiguous
-// bytes of the row; the workgroup walks 16 rows per step and the loads of the
-// next step are in flight while the current one is computed.  For each pair it
-// re-ranks the p latent coordinates of u = Z_i - Z_j, forms the latent distance
-// delta, the residual r = delta - Delta_ij, r^2 and the gradient term
-// r * d delta / d Z_i (added to row i, subtracted from column j; the common
-// factor 2 -- 2 * 2^(1-nu) for p = 2 Gini -- is applied once per point).
-//
-// Reduction.  A unit writes one partial per row (complete for that tile), one
-// partial per column and its stress.  A second launch sums, for every point, the
-// row partials of its tile row and the column partials of its tile column in a
-// fixed order (sixteen interleaved Neumaier sums, one wave each over 64
-// consecutive points, combined in index order), and either writes the
-// gradient or takes the descent step.  No floating-point
-// atomics anywhere: results are bitwise reproducible and independent of
-// scheduling and of how many instances share a launch.
-#include <hip/hip_ext.h>
-
-#include "common.hpp"
-#include "kernels.hpp"
+// k_stress.hip -- raw-stress instantiations of the stress kernels (the
+// templates live in stress_impl.hpp), the reduction launch, and the host-side
+// launchers of both losses.
+#include "stress_impl.hpp"
 
 namespace gmds {
-
-constexpr int kWG = 256;
-constexpr int kLPR = 16;                 // lanes per tile row = one DPP row
-constexpr int kRPS = kWG / kLPR;         // rows per step
-constexpr int kSplit = 16;               // interleaved partial sums per point in the reduction
-constexpr int kBatch = 8;                // loads in flight per partial sum
-constexpr int kWaves = kStressWaves;     // waves per workgroup (one stress partial each)
-static_assert(kWaves * 64 == kWG, "one stress partial per wave");
-
-typedef float f4v __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(1))) const f4v gf4;
-typedef __attribute__((address_space(1))) const float gfl;
-typedef __attribute__((address_space(1))) float gflw;
-
-__device__ __forceinline__ gfl* gp(const float* p) { return (gfl*)p; }
-__device__ __forceinline__ gflw* gpw(float* p) { return (gflw*)p; }
-
-template <int T> struct TileShape {
-    static constexpr int CPT = T / kLPR;      // columns per thread
-    static constexpr int NQ = CPT / 4;        // 16-byte loads per thread and row
-    static constexpr int UR = 64;             // rows per work unit
-    static constexpr int STEPS = UR / kRPS;   // pipelined steps per unit
-    static constexpr int UNITS = T / UR;      // work units per tile
-    // Delta steps in flight per thread: the whole unit while that costs at
-    // most 8 loads (32 registers), else two
-    static constexpr int DEPTH = (NQ * STEPS <= 8) ? STEPS : 2;
-};
-
-template <int P, int LAT>
-struct PG_ { static constexpr int value = (P == 2 && LAT == 0) ? 1 : P; };
-
-// Sum over the 16 lanes of a DPP row by rotations; every lane ends with a
-// total and lane 0 of the row is the one used (fixed order).
-template <int CTRL>
-__device__ __forceinline__ float dpp_f(float x) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float row16_sum(float x) {
-    x += dpp_f<0x128>(x);   // row_ror:8
-    x += dpp_f<0x124>(x);   // row_ror:4
-    x += dpp_f<0x122>(x);   // row_ror:2
-    x += dpp_f<0x121>(x);   // row_ror:1
-    return x;
-}
-
-// Stress term of one pair and its gradient term g (without the common factor).
-// MASK: `valid` zeroes pairs outside the strict upper triangle or past n.
-// u_c = fl32(Z_i,c - Z_j,c).  Gini: doubled midranks t_c of u over its p
-// coordinates, a_c = (p/2) W_p[t_c], delta = sum_c u_c a_c, g = r a.
-// Euclid: delta = |u|, g = r u / |u| (0 when u = 0).
-template <int P, int LAT, bool GRAD, bool MASK>
-__device__ __forceinline__ float pair_term(const float (&zi)[P], const float (&zj)[P], float d, bool valid,
-                                           int p, const InstDesc& D, float (&g)[PG_<P, LAT>::value]) {
-    constexpr int PG = PG_<P, LAT>::value;
-    float u[P];
-#pragma unroll
-    for (int c = 0; c < P; ++c) u[c] = zi[c] - zj[c];
-    if constexpr (P == 2 && LAT == 0) {
-        // t = (2,4) if u1 < u2, (4,2) if u1 > u2, (3,3) on a tie, hence
-        // delta = 2^(1-nu) |u2 - u1| and a = 2^(1-nu) sgn(u2 - u1) (-1, +1);
-        // g keeps r sgn(u2 - u1), the second component.
-        const float w = u[1] - u[0];
-        float r = fmaf(D.c2, fabsf(w), -d);
-        if constexpr (MASK) r = valid ? r : 0.f;
-        if constexpr (GRAD) g[0] = (w > 0.f) ? r : ((w < 0.f) ? -r : 0.f);
-        return r * r;
-    } else if constexpr (P == 3 && LAT == 0) {
-        // Untied u takes the doubled midranks (2, 4, 6) in sorted order, and the
-        // middle weight is exactly 0, so delta = a_max u_max + a_min u_min with
-        // a_max = (3/2) W_3[6] = -a_min.  A tie (rare) takes the general rule.
-        const float mx = fmaxf(fmaxf(u[0], u[1]), u[2]);
-        const float mn = fminf(fminf(u[0], u[1]), u[2]);
-        const bool tie = (u[0] == u[1]) || (u[1] == u[2]) || (u[0] == u[2]);
-        float r, a[3];
-        if (!tie) {
-            const float wmax = D.wtab[4], wmin = D.wtab[0];
-            r = fmaf(wmax, mx, wmin * mn) - d;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) a[c] = (u[c] == mx) ? wmax : ((u[c] == mn) ? wmin : 0.f);
-        } else {
-            float delta = 0.f;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                int t = 1;
-#pragma unroll
-                for (int k = 0; k < 3; ++k) t += (u[k] < u[c]) ? 2 : ((u[k] == u[c]) ? 1 : 0);
-                float w = D.wtab[0];
-#pragma unroll
-                for (int q = 1; q < 5; ++q) w = (t - 2 == q) ? D.wtab[q] : w;
-                a[c] = w;
-                delta = fmaf(u[c], w, delta);
-            }
-            r = delta - d;
-        }
-        if constexpr (MASK) r = valid ? r : 0.f;
-        if constexpr (GRAD) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) g[c] = r * a[c];
-        }
-        return r * r;
-    } else if constexpr (LAT == 0) {
-        float a[P];
-        float delta = 0.f;
-#pragma unroll
-        for (int c = 0; c < P; ++c) {
-            int t = 1;
-#pragma unroll
-            for (int k = 0; k < P; ++k)
-                if (P != kMaxP || k < p) t += (u[k] < u[c]) ? 2 : ((u[k] == u[c]) ? 1 : 0);
-            float w = D.wtab[0];
-#pragma unroll
-            for (int q = 1; q < 2 * P - 1; ++q) w = (t - 2 == q) ? D.wtab[q] : w;
-            if (P == kMaxP && c >= p) w = 0.f;
-            a[c] = w;
-            delta = fmaf(u[c], w, delta);
-        }
-        float r = delta - d;
-        if constexpr (MASK) r = valid ? r : 0.f;
-        if constexpr (GRAD) {
-#pragma unroll
-            for (int c = 0; c < PG; ++c) g[c] = r * a[c];
-        }
-        return r * r;
-    } else {
-        float ss = 0.f;
-#pragma unroll
-        for (int c = 0; c < P; ++c) ss = fmaf(u[c], u[c], ss);
-        const float rs = (ss > 0.f) ? rsqrtf(ss) : 0.f;
-        float r = fmaf(ss, rs, -d);
-        if constexpr (MASK) r = valid ? r : 0.f;
-        if constexpr (GRAD) {
-            const float f = r * rs;
-#pragma unroll
-            for (int c = 0; c < PG; ++c) g[c] = f * u[c];
-        }
-        return r * r;
-    }
-}
-
-// Fixed-shape workgroup sum of compensated pairs; every thread gets the total.
-__device__ Comp wg_sum(Comp v, float* lds) {
-    const int tid = threadIdx.x;
-    __syncthreads();
-    lds[tid] = v.hi;
-    lds[kWG + tid] = v.lo;
-    __syncthreads();
-#pragma unroll
-    for (int st = kWG / 2; st > 0; st >>= 1) {
-        if (tid < st) {
-            Comp a;
-            a.hi = lds[tid];
-            a.lo = lds[kWG + tid];
-            Comp b;
-            b.hi = lds[tid + st];
-            b.lo = lds[kWG + tid + st];
-            a.add(b);
-            lds[tid] = a.hi;
-            lds[kWG + tid] = a.lo;
-        }
-        __syncthreads();
-    }
-    Comp r;
-    r.hi = lds[0];
-    r.lo = lds[kWG];
-    __syncthreads();
-    return r;
-}
-
-// LDS floats used by one unit: the latent rows and columns of the unit, the
-// column reduction (16 row groups x T) and the stress tree.
-template <int P, int T>
-constexpr int unit_lds_floats() {
-    return TileShape<T>::UR * P + T * P + (kRPS * T > 2 * kWG ? kRPS * T : 2 * kWG);
-}
-
-// Stream unit `sub` (rows I*T + sub*UR ..) of tile lt = (I, J) of instance D:
-// row partials rowpart[lt][row], column partials colpart[lt][sub][col] (GRAD)
-// and its stress, one (hi, lo) per wave: sigpart[(lt*UNITS + sub)*kWaves + w].
-template <int P, int LAT, int T, bool GRAD, bool MASK>
-__device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int64_t J, float* lds) {
-    constexpr int CPT = TileShape<T>::CPT;
-    constexpr int NQ = TileShape<T>::NQ;
-    constexpr int UNITS = TileShape<T>::UNITS;
-    constexpr int UR = TileShape<T>::UR;
-    constexpr int STEPS = TileShape<T>::STEPS;
-    constexpr int PG = PG_<P, LAT>::value;
-    const int tid = threadIdx.x;
-    const int c4 = tid % kLPR;
-    const int rr = tid / kLPR;
-    const int64_t n = D.n;
-    const int64_t i0 = I * T + sub * UR;
-    const int64_t j0 = J * T;
-    const int p = (P == kMaxP) ? D.p : P;
-    gfl* Zg = gp(D.Z);
-    float* zrow = lds;                                  // [UR][P]
-    float* zcol = lds + UR * P;                         // [T][P]
-    float* red = zcol + T * P;
-
-    // Delta loads for one step of the unit (unmasked: 16-byte global loads)
-    auto load_step = [&](int s, f4v (&buf)[NQ]) {
-        const int64_t i = i0 + s * kRPS + rr;
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int64_t jb = j0 + 4 * (c4 + q * kLPR);
-            if constexpr (!MASK) {
-                buf[q] = *(gf4*)(D.Delta + i * D.ldd + jb);
-            } else {
-                f4v v = {0.f, 0.f, 0.f, 0.f};
-                if (i < n && jb + 3 > i && jb < n) {
-                    const float* Dr = D.Delta + i * D.ldd;
-                    if (D.vec && jb + 3 < n) {
-                        v = *(gf4*)(Dr + jb);
-                    } else {
-                        if (jb + 0 < n && jb + 0 > i) v.x = gp(Dr)[jb + 0];
-                        if (jb + 1 < n && jb + 1 > i) v.y = gp(Dr)[jb + 1];
-                        if (jb + 2 < n && jb + 2 > i) v.z = gp(Dr)[jb + 2];
-                        if (jb + 3 < n && jb + 3 > i) v.w = gp(Dr)[jb + 3];
-                    }
-                }
-                buf[q] = v;
-            }
-        }
-    };
-    // The latent rows and columns of the unit are requested first (coalesced),
-    // then the first DEPTH steps of Delta, so that both are in flight together
-    // while the coordinates wait for their LDS slots; afterwards step
-    // s + DEPTH is loaded into the slot that step s has just been computed from.
-    constexpr int NZR = (UR * P + kWG - 1) / kWG;
-    constexpr int NZC = (T * P + kWG - 1) / kWG;
-    float zr_[NZR], zc_[NZC];
-#pragma unroll
-    for (int k = 0; k < NZR; ++k) {
-        const int x = tid + k * kWG;
-        const int r = x / P, c = x % P;
-        const int64_t i = i0 + r;
-        zr_[k] = (x < UR * P && c < p && (!MASK || i < n)) ? Zg[i * D.ldz + c] : 0.f;
-    }
-#pragma unroll
-    for (int k = 0; k < NZC; ++k) {
-        const int x = tid + k * kWG;
-        const int r = x / P, c = x % P;
-        const int64_t j = j0 + r;
-        zc_[k] = (x < T * P && c < p && (!MASK || j < n)) ? Zg[j * D.ldz + c] : 0.f;
-    }
-    constexpr int DEPTH = TileShape<T>::DEPTH;
-    f4v buf[DEPTH][NQ];
-#pragma unroll
-    for (int s = 0; s < DEPTH; ++s) load_step(s, buf[s]);
-#pragma unroll
-    for (int k = 0; k < NZR; ++k)
-        if (tid + k * kWG < UR * P) zrow[tid + k * kWG] = zr_[k];
-#pragma unroll
-    for (int k = 0; k < NZC; ++k)
-        if (tid + k * kWG < T * P) zcol[tid + k * kWG] = zc_[k];
-    __syncthreads();
-    float zj[CPT][P];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-            for (int c = 0; c < P; ++c) zj[q * 4 + e][c] = zcol[(4 * (c4 + q * kLPR) + e) * P + c];
-    float colacc[CPT][PG];
-#pragma unroll
-    for (int x = 0; x < CPT; ++x)
-#pragma unroll
-        for (int c = 0; c < PG; ++c) colacc[x][c] = 0.f;
-    Comp sig;
-
-    auto compute_step = [&](int s, const f4v (&buf)[NQ]) {
-        const int il = sub * UR + s * kRPS + rr;           // row within the tile
-        const int64_t i = I * T + il;
-        float zi[P];
-#pragma unroll
-        for (int c = 0; c < P; ++c) zi[c] = zrow[(s * kRPS + rr) * P + c];
-        float rowacc[PG];
-#pragma unroll
-        for (int c = 0; c < PG; ++c) rowacc[c] = 0.f;
-        float sst = 0.f;
-#pragma unroll
-        for (int q = 0; q < NQ; ++q)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int x = q * 4 + e;
-                const int64_t j = j0 + 4 * (c4 + q * kLPR) + e;
-                const bool valid = !MASK || ((j > i) && (j < n) && (i < n));
-                float g[PG];
-                sst += pair_term<P, LAT, GRAD, MASK>(zi, zj[x], buf[q][e], valid, p, D, g);
-                if constexpr (GRAD) {
-#pragma unroll
-                    for (int c = 0; c < PG; ++c) {
-                        rowacc[c] += g[c];
-                        colacc[x][c] += g[c];
-                    }
-                }
-            }
-        if constexpr (GRAD) {
-#pragma unroll
-            for (int c = 0; c < PG; ++c) {
-                const float tot = row16_sum(rowacc[c]);
-                if (c4 == 0 && (!MASK || i < n)) gpw(D.rowpart)[(lt * T + il) * PG + c] = tot;
-            }
-        }
-        sig.add(sst);
-    };
-
-#pragma unroll
-    for (int s = 0; s < STEPS; ++s) {
-        compute_step(s, buf[s % DEPTH]);
-        if (s + DEPTH < STEPS) load_step(s + DEPTH, buf[s % DEPTH]);
-    }
-
-    if constexpr (GRAD) {
-        // column partials: the 16 row groups hold partial sums of each column
-#pragma unroll
-        for (int c = 0; c < PG; ++c) {
-            __syncthreads();
-#pragma unroll
-            for (int q = 0; q < NQ; ++q)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) red[rr * T + 4 * (c4 + q * kLPR) + e] = colacc[q * 4 + e][c];
-            __syncthreads();
-            for (int x = tid; x < T; x += kWG) {
-                float acc = 0.f;
-#pragma unroll
-                for (int r = 0; r < kRPS; ++r) acc += red[r * T + x];
-                gpw(D.colpart)[((lt * UNITS + sub) * T + x) * PG + c] = acc;
-            }
-        }
-    }
-    // stress: one compensated partial per wave (fixed butterfly, lane 0's copy)
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        Comp other;
-        other.hi = __shfl_xor(sig.hi, o, 64);
-        other.lo = __shfl_xor(sig.lo, o, 64);
-        sig.add(other);
-    }
-    if ((tid & 63) == 0) {
-        const int64_t slot = (lt * UNITS + sub) * kWaves + (tid >> 6);
-        gpw(D.sigpart)[2 * slot + 0] = sig.hi;
-        gpw(D.sigpart)[2 * slot + 1] = sig.lo;
-    }
-}
-
-template <int P, int LAT, int T, bool GRAD>
-__device__ __forceinline__ void stress_unit(const InstDesc& D, int64_t lu, float* lds) {
-    constexpr int UNITS = TileShape<T>::UNITS;
-    const int64_t lt = lu / UNITS;
-    const int sub = (int)(lu % UNITS);
-    int64_t I, J;
-    tri_decode(lt, D.nb, I, J);
-    if (I * T + (int64_t)sub * TileShape<T>::UR >= D.n) return;   // rows past n: nothing to do
-    const bool interior = D.vec && (I < J) && ((J + 1) * T <= D.n);
-    if (interior) unit_body<P, LAT, T, GRAD, false>(D, lt, sub, I, J, lds);
-    else unit_body<P, LAT, T, GRAD, true>(D, lt, sub, I, J, lds);
-}
-
-// ---------------------------------------------------------------- reduction
-// Every sum below has a fixed shape that does not depend on how many threads
-// execute it, so the reduction launch (kRedWG threads) and the persistent
-// solver (kWG threads) produce bitwise identical results.
-constexpr int kRedWG = 1024;             // threads of a reduction block
-constexpr int kNPT = 64;                 // points per reduction group (one per lane)
-constexpr int kVT = 1024;                // virtual threads of a stress slice
-
-// Partial gradient of point k: terms t = s, s + kSplit, ... of the sequence
-// "row partials of its tile row (tiles (b, b..nb-1)), then column partials of
-// its tile column (every unit of tiles (0..b, b))", summed (Neumaier) in
-// increasing t.  The loads of a batch are in flight together; an absent term
-// adds an exact 0.
-template <int P, int LAT, int T>
-__device__ __forceinline__ void point_partial(const InstDesc& D, int64_t k, int s, Comp (&acc)[PG_<P, LAT>::value]) {
-    constexpr int PG = PG_<P, LAT>::value;
-    constexpr int UNITS = TileShape<T>::UNITS;
-    const int64_t b = k / T;
-    const int64_t kl = k % T;
-    const int64_t nb = D.nb;
-    const int64_t nrow = nb - b;
-    const int64_t nterm = nrow + (b + 1) * UNITS;
-    const int64_t last_lt = tri_count(nb) - 1;
-    gfl* rp = gp(D.rowpart);
-    gfl* cp = gp(D.colpart);
-    for (int64_t t0 = s; t0 < nterm; t0 += (int64_t)kSplit * kBatch) {
-        float v[kBatch][PG];
-#pragma unroll
-        for (int q = 0; q < kBatch; ++q) {
-            const int64_t t = t0 + (int64_t)q * kSplit;
-            if (t < nrow) {
-                const int64_t lt = tri_index(b, b + t, nb);
-#pragma unroll
-                for (int c = 0; c < PG; ++c) v[q][c] = rp[(lt * T + kl) * PG + c];
-            } else {
-                const int64_t tc = t - nrow;
-                const int64_t I = tc / UNITS;
-                const int u = (int)(tc % UNITS);
-                const int64_t lt = tri_index(I, b, nb);
-                // units past n (only in the last tile) were never written
-                const bool ok = (t < nterm) && !(lt == last_lt && I * T + (int64_t)u * TileShape<T>::UR >= D.n);
-#pragma unroll
-                for (int c = 0; c < PG; ++c) v[q][c] = ok ? -cp[((lt * UNITS + u) * T + kl) * PG + c] : 0.f;
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < kBatch; ++q)
-#pragma unroll
-            for (int c = 0; c < PG; ++c) acc[c].add(v[q][c]);
-    }
-}
-
-// Gradient of the kNPT points k0 .. k0+kNPT-1: the kSplit partial sums of each
-// point (one wave per partial sum: 64 consecutive points, coalesced loads)
-// are added in index order, scaled by the common factor and applied.  NT is
-// the number of threads executing the call.  LDS: 2 * kSplit * kNPT * PG floats.
-template <int P, int LAT, int T, int NT>
-__device__ void reduce_group(const InstDesc& D, int64_t k0, int mode, float* lds) {
-    constexpr int PG = PG_<P, LAT>::value;
-    const int tid = threadIdx.x;
-    const int p = (P == kMaxP) ? D.p : P;
-    // the combining threads fetch what they update before the partial sums
-    // arrive, so that its latency overlaps theirs
-    const bool comb = tid < kNPT && k0 + tid < D.n;
-    float zold[P];
-    float sc = 1.f;
-    if (comb) {
-        if (mode == kModeGrad) {
-            if (D.grad_out) sc = *D.grad_out;
-        } else {
-#pragma unroll
-            for (int c = 0; c < P; ++c) zold[c] = (c < p) ? D.Z[(k0 + tid) * D.ldz + c] : 0.f;
-        }
-    }
-    for (int item = tid; item < kSplit * kNPT; item += NT) {
-        const int sp = item / kNPT;
-        const int pl = item % kNPT;
-        const int64_t k = k0 + pl;
-        Comp acc[PG];
-        if (k < D.n) point_partial<P, LAT, T>(D, k, sp, acc);
-#pragma unroll
-        for (int c = 0; c < PG; ++c) {
-            lds[((c * kSplit + sp) * kNPT + pl) * 2] = acc[c].hi;
-            lds[((c * kSplit + sp) * kNPT + pl) * 2 + 1] = acc[c].lo;
-        }
-    }
-    __syncthreads();
-    if (comb) {
-        const int pl = tid;
-        const int64_t k = k0 + pl;
-        Comp tot[PG];
-#pragma unroll
-        for (int c = 0; c < PG; ++c)
-            for (int q = 0; q < kSplit; ++q) {
-                Comp x;
-                x.hi = lds[((c * kSplit + q) * kNPT + pl) * 2];
-                x.lo = lds[((c * kSplit + q) * kNPT + pl) * 2 + 1];
-                tot[c].add(x);
-            }
-        float G[P];
-        if constexpr (P == 2 && LAT == 0) {
-            const float v = 2.f * D.c2 * tot[0].value();
-            G[0] = -v;
-            G[1] = v;
-        } else {
-#pragma unroll
-            for (int c = 0; c < P; ++c) G[c] = 2.f * tot[c].value();
-        }
-        if (mode == kModeGrad) {
-#pragma unroll
-            for (int c = 0; c < P; ++c)
-                if (c < p) D.gradZ[k * D.ldg + c] = sc * G[c];
-        } else {
-#pragma unroll
-            for (int c = 0; c < P; ++c)
-                if (c < p) D.Z[k * D.ldz + c] = zold[c] - D.eta * G[c];
-        }
-    }
-    __syncthreads();
-}
-
-// Stress of instance D from the per-wave unit partials (units past n, only in
-// the last tile, hold nothing), in contiguous slices.  A slice is a fixed
-// shape sum: virtual thread v < kVT adds partials a+v, a+v+kVT, ... in order,
-// then a fixed binary tree over the kVT values; slices are added in order.
-constexpr int kSigSlices = 32;
-
-template <int T>
-__device__ __forceinline__ int64_t sigma_count(const InstDesc& D) {
-    return tri_count(D.nb) * TileShape<T>::UNITS * kWaves;
-}
-// About kVT * kBatch partials per slice, at most kSigSlices (one slice --
-// written directly, no combining step -- for small instances).
-template <int T>
-__device__ __forceinline__ int sigma_slices(const InstDesc& D) {
-    const int64_t s = sigma_count<T>(D) / (kVT * kBatch);
-    return (int)(s < 1 ? 1 : (s > kSigSlices ? kSigSlices : s));
-}
-
-// LDS: 2 * kVT floats.  All NT threads return the slice sum.
-template <int T, int NT>
-__device__ Comp sigma_slice(const InstDesc& D, int slice, float* lds) {
-    constexpr int UNITS = TileShape<T>::UNITS;
-    const int64_t nt = tri_count(D.nb);
-    const int64_t cnt = sigma_count<T>(D);
-    const int ns = sigma_slices<T>(D);
-    const int64_t a = cnt * slice / ns;
-    const int64_t e = cnt * (slice + 1) / ns;
-    gfl* sp = gp(D.sigpart);
-    for (int vt = threadIdx.x; vt < kVT; vt += NT) {
-        Comp acc;
-        for (int64_t t0 = a + vt; t0 < e; t0 += (int64_t)kVT * kBatch) {
-            float hv[kBatch], lv[kBatch];
-#pragma unroll
-            for (int q = 0; q < kBatch; ++q) {
-                const int64_t t = t0 + (int64_t)q * kVT;
-                const int64_t lu = t / kWaves;
-                const int u = (int)(lu % UNITS);
-                const bool ok = (t < e) && !(lu / UNITS == nt - 1 && (D.nb - 1) * T + (int64_t)u * TileShape<T>::UR >= D.n);
-                hv[q] = ok ? sp[2 * t] : 0.f;
-                lv[q] = ok ? sp[2 * t + 1] : 0.f;
-            }
-#pragma unroll
-            for (int q = 0; q < kBatch; ++q) {
-                Comp x;
-                x.hi = hv[q];
-                x.lo = lv[q];
-                acc.add(x);
-            }
-        }
-        lds[vt] = acc.hi;
-        lds[kVT + vt] = acc.lo;
-    }
-    __syncthreads();
-    for (int st = kVT / 2; st > 0; st >>= 1) {
-        for (int x = threadIdx.x; x < st; x += NT) {
-            Comp u;
-            u.hi = lds[x];
-            u.lo = lds[kVT + x];
-            Comp w;
-            w.hi = lds[x + st];
-            w.lo = lds[kVT + x + st];
-            u.add(w);
-            lds[x] = u.hi;
-            lds[kVT + x] = u.lo;
-        }
-        __syncthreads();
-    }
-    Comp r;
-    r.hi = lds[0];
-    r.lo = lds[kVT];
-    __syncthreads();
-    return r;
-}
-
-template <int T, int NT>
-__device__ Comp instance_sigma(const InstDesc& D, float* lds) {
-    const int ns = sigma_slices<T>(D);
-    if (ns == 1) return sigma_slice<T, NT>(D, 0, lds);
-    Comp tot;
-    for (int sl = 0; sl < ns; ++sl) tot.add(sigma_slice<T, NT>(D, sl, lds));
-    return tot;
-}
-
-__device__ __forceinline__ void write_sigma(const InstDesc& D, int mode, int it, const Comp& s) {
-    if (threadIdx.x != 0) return;
-    if (mode == kModeDescent) {
-        if (D.sigma_hist) D.sigma_hist[it] = s.hi + s.lo;
-        if (D.ks_hist) {
-            const double den = (double)D.dsumsq[0] + (double)D.dsumsq[1];
-            const double num = (double)s.hi + (double)s.lo;
-            D.ks_hist[it] = den > 0.0 ? (float)sqrt(num / den) : 0.f;
-        }
-    } else if (D.out_sigma) {
-        D.out_sigma[0] = s.hi;
-        D.out_sigma[1] = s.lo;
-    }
-}
-
-// Map a global unit index to its instance (descriptors sorted by tile_off,
-// which counts units).
-__device__ __forceinline__ int find_instance(const InstDesc* dd, int n_inst, int64_t q) {
-    int lo = 0, hi = n_inst - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (dd[mid].tile_off <= q) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-template <int P, int LAT, int T, bool GRAD>
-__global__ __launch_bounds__(kWG) void k_stress_units(const InstDesc* __restrict__ dd, int n_inst, int64_t q_base) {
-    __shared__ float lds[unit_lds_floats<P, T>()];
-    const int64_t q = (int64_t)blockIdx.x + q_base;
-    const int k = find_instance(dd, n_inst, q);
-    const InstDesc D = dd[k];
-    stress_unit<P, LAT, T, GRAD>(D, q - D.tile_off, lds);
-}
-
-// Number of reduction blocks of an instance: its stress slices, then one
-// block per kNPT points.
-template <int T>
-__device__ __forceinline__ int64_t reduce_blocks(const InstDesc& D) {
-    return sigma_slices<T>(D) + (D.n + kNPT - 1) / kNPT;
-}
-
-template <int PG>
-constexpr int reduce_lds_floats() {
-    return 2 * kSplit * kNPT * PG > 2 * kVT ? 2 * kSplit * kNPT * PG : 2 * kVT;
-}
-
-// Reduction launch over the concatenated blocks of all instances (block
-// offsets in red_off).  The first blocks of an instance sum one slice of its
-// stress each (with several slices, the last to finish adds them in order);
-// the following blocks take kNPT points each.
-template <int P, int LAT, int T>
-__global__ __launch_bounds__(kRedWG) void k_stress_reduce(const InstDesc* __restrict__ dd, int n_inst,
-                                                          int64_t q_base, int mode, int it) {
-    constexpr int PG = PG_<P, LAT>::value;
-    __shared__ float lds[reduce_lds_floats<PG>()];
-    __shared__ int last;
-    const int64_t q = (int64_t)blockIdx.x + q_base;
-    int lo = 0, hi = n_inst - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (dd[mid].red_off <= q) lo = mid;
-        else hi = mid - 1;
-    }
-    const InstDesc& D = dd[lo];
-    const int64_t b = q - D.red_off;
-    const int ns = sigma_slices<T>(D);
-    if (b < ns) {
-        const Comp part = sigma_slice<T, kRedWG>(D, (int)b, lds);
-        if (threadIdx.x == 0) {
-            if (ns == 1) {
-                write_sigma(D, mode, it, part);
-            } else {
-                gpw(D.sigslice)[2 * b] = part.hi;
-                gpw(D.sigslice)[2 * b + 1] = part.lo;
-                __threadfence();
-                last = (atomicAdd(D.instcnt, 1u) + 1 == (uint32_t)ns) ? 1 : 0;
-            }
-        }
-        if (ns == 1) return;
-        __syncthreads();
-        if (last && threadIdx.x == 0) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            Comp tot;
-            for (int sl = 0; sl < ns; ++sl) {
-                Comp x;
-                x.hi = gp(D.sigslice)[2 * sl];
-                x.lo = gp(D.sigslice)[2 * sl + 1];
-                tot.add(x);
-            }
-            write_sigma(D, mode, it, tot);
-            __hip_atomic_store(D.instcnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        return;
-    }
-    if (mode == kModeSigma) return;
-    reduce_group<P, LAT, T, kRedWG>(D, (b - ns) * kNPT, mode, lds);
-}
 
 __global__ void k_fill_u32(uint32_t* p, int64_t count, uint32_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) p[i] = v;
-}
-
-// Persistent solver.  Queue item q = (iteration it, instance k, local unit),
-// iteration-major, instances in the host's order.  A workgroup pops q, waits
-// until instance k has finished iteration it-1 (epoch[k] >= it), streams the
-// unit and counts it done (release fence, integer counter); the workgroup that
-// completes the last unit of (k, it) reduces the whole instance with the same
-// fixed-order sums as the reduction launch, takes the step, resets the counter
-// and publishes epoch[k] = it + 1.  Items are popped in queue order and every
-// item waits only on items popped before it, whose workgroups are already
-// running, so the queue drains whatever the number of resident workgroups.  A
-// wait longer than spin_limit ticks of the constant-rate device clock sets the
-// abort status; every workgroup then stops popping work and the kernel ends.
-template <int P, int LAT, int T>
-__global__ __launch_bounds__(kWG) void k_solve_persistent(const InstDesc* __restrict__ dd, int n_inst,
-                                                          const int64_t* __restrict__ prefix,
-                                                          int64_t per_iter, int iters, SolveCtl* ctl,
-                                                          uint32_t* epoch, int64_t spin_limit) {
-    constexpr int PG = PG_<P, LAT>::value;
-    constexpr int UNITS = TileShape<T>::UNITS;
-    constexpr int NL1 = unit_lds_floats<P, T>();
-    constexpr int NL2 = reduce_lds_floats<PG>();
-    __shared__ float lds[NL1 > NL2 ? NL1 : NL2];
-    __shared__ int64_t sh_q;
-    __shared__ int sh_flag;
-    const int tid = threadIdx.x;
-    const int64_t total = per_iter * (int64_t)iters;
-    for (;;) {
-        if (tid == 0) {
-            const uint32_t st = __hip_atomic_load(&ctl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            int64_t q = total;
-            if (st == kStatusOk) q = (int64_t)atomicAdd(&ctl->head, 1ull);
-            sh_q = q;
-        }
-        __syncthreads();
-        const int64_t q = sh_q;
-        __syncthreads();
-        if (q >= total) break;
-        const int it = (int)(q / per_iter);
-        const int64_t r = q % per_iter;
-        int lo = 0, hi = n_inst - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (prefix[mid] <= r) lo = mid;
-            else hi = mid - 1;
-        }
-        const int k = lo;
-        const int64_t lu = r - prefix[k];
-        if (tid == 0) {
-            int ok = 1;
-            if (__hip_atomic_load(&epoch[k], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < (uint32_t)it) {
-                const uint64_t t0 = wall_clock64();
-                while (__hip_atomic_load(&epoch[k], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < (uint32_t)it) {
-                    __builtin_amdgcn_s_sleep(2);
-                    if (__hip_atomic_load(&ctl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kStatusOk) {
-                        ok = 0;
-                        break;
-                    }
-                    if ((int64_t)(wall_clock64() - t0) > spin_limit) {
-                        __hip_atomic_store(&ctl->status, (uint32_t)kStatusTimeout, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                        ok = 0;
-                        break;
-                    }
-                }
-            }
-            sh_flag = ok;
-        }
-        __syncthreads();
-        if (!sh_flag) {
-            __syncthreads();
-            continue;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        const InstDesc D = dd[k];
-        stress_unit<P, LAT, T, true>(D, lu, lds);
-        __threadfence();
-        __syncthreads();
-        if (tid == 0) {
-            const uint32_t old = atomicAdd(D.instcnt, 1u);
-            sh_flag = (old + 1 == (uint32_t)(tri_count(D.nb) * UNITS)) ? 1 : 0;
-        }
-        __syncthreads();
-        if (sh_flag) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            const Comp s = instance_sigma<T, kWG>(D, lds);
-            write_sigma(D, kModeDescent, it, s);
-            for (int64_t k0 = 0; k0 < D.n; k0 += kNPT) reduce_group<P, LAT, T, kWG>(D, k0, kModeDescent, lds);
-            __threadfence();
-            __syncthreads();
-            if (tid == 0) {
-                __hip_atomic_store(D.instcnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&epoch[k], (uint32_t)(it + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-        __syncthreads();
-    }
-}
-
-// ------------------------------------------------------------- dispatch
-static int p_bucket(int p) { return p <= 4 ? p : kMaxP; }
-
-// A launch on stream s; with both events set (profiling), the runtime stamps
-// them at the start and the end of the kernel itself.
-struct Launch {
-    hipStream_t s;
-    LaunchTimer tm;
-};
-
-template <typename K, typename... A>
-static hipError_t launch_k(K kernel, dim3 grid, dim3 block, const Launch& L, A... args) {
-    if (L.tm.start && L.tm.stop)
-        hipExtLaunchKernelGGL(kernel, grid, block, 0, L.s, L.tm.start, L.tm.stop, 0, args...);
-    else
-        hipLaunchKernelGGL(kernel, grid, block, 0, L.s, args...);
-    return hipGetLastError();
-}
-
-template <int P, int LAT, int T>
-static hipError_t units_impl(const InstDesc* dd, int n_inst, int64_t count, int64_t qb, bool grad, const Launch& L) {
-    if (count <= 0) return hipSuccess;
-    if (grad) return launch_k(k_stress_units<P, LAT, T, true>, dim3((unsigned)count), dim3(kWG), L, dd, n_inst, qb);
-    return launch_k(k_stress_units<P, LAT, T, false>, dim3((unsigned)count), dim3(kWG), L, dd, n_inst, qb);
 }
 
 template <int P, int LAT, int T>
@@ -827,43 +18,36 @@ static hipError_t reduce_impl(const InstDesc* dd, int n_inst, int64_t blocks, in
 }
 
 template <int LAT, int T>
-static hipError_t dispatch_p(int which, const InstDesc* dd, int n_inst, int64_t count, int64_t qb, int p, bool grad,
-                             int64_t max_n, int mode, int it, const Launch& L) {
-#define GMDS_CALL(PP)                                                                 \
-    return which == 0 ? units_impl<PP, LAT, T>(dd, n_inst, count, qb, grad, L)         \
-                      : reduce_impl<PP, LAT, T>(dd, n_inst, max_n, qb, mode, it, L);  /* max_n: block count */
+static hipError_t reduce_dispatch_p(const InstDesc* dd, int n_inst, int64_t blocks, int64_t qb, int p, int mode,
+                                    int it, const Launch& L) {
     switch (p_bucket(p)) {
-        case 1: GMDS_CALL(1)
-        case 2: GMDS_CALL(2)
-        case 3: GMDS_CALL(3)
-        case 4: GMDS_CALL(4)
-        default: GMDS_CALL(kMaxP)
+        case 1: return reduce_impl<1, LAT, T>(dd, n_inst, blocks, qb, mode, it, L);
+        case 2: return reduce_impl<2, LAT, T>(dd, n_inst, blocks, qb, mode, it, L);
+        case 3: return reduce_impl<3, LAT, T>(dd, n_inst, blocks, qb, mode, it, L);
+        case 4: return reduce_impl<4, LAT, T>(dd, n_inst, blocks, qb, mode, it, L);
+        default: return reduce_impl<kMaxP, LAT, T>(dd, n_inst, blocks, qb, mode, it, L);
     }
-#undef GMDS_CALL
 }
 
 template <int T>
-static hipError_t dispatch_lat(int which, const InstDesc* dd, int n_inst, int64_t count, int64_t qb, int p,
-                               int latent, bool grad, int64_t max_n, int mode, int it, const Launch& L) {
-    if (latent == 0) return dispatch_p<0, T>(which, dd, n_inst, count, qb, p, grad, max_n, mode, it, L);
-    return dispatch_p<1, T>(which, dd, n_inst, count, qb, p, grad, max_n, mode, it, L);
-}
-
-static hipError_t dispatch(int which, const InstDesc* dd, int n_inst, int64_t count, int64_t qb, int p, int latent,
-                           int T, bool grad, int64_t max_n, int mode, int it, const Launch& L) {
-    if (T == 64) return dispatch_lat<64>(which, dd, n_inst, count, qb, p, latent, grad, max_n, mode, it, L);
-    if (T == 128) return dispatch_lat<128>(which, dd, n_inst, count, qb, p, latent, grad, max_n, mode, it, L);
-    return dispatch_lat<256>(which, dd, n_inst, count, qb, p, latent, grad, max_n, mode, it, L);
+static hipError_t reduce_dispatch_lat(const InstDesc* dd, int n_inst, int64_t blocks, int64_t qb, int p, int latent,
+                                      int mode, int it, const Launch& L) {
+    if (latent == 0) return reduce_dispatch_p<0, T>(dd, n_inst, blocks, qb, p, mode, it, L);
+    return reduce_dispatch_p<1, T>(dd, n_inst, blocks, qb, p, mode, it, L);
 }
 
 hipError_t launch_stress_units(const InstDesc* dd, int n_inst, int64_t count, int64_t q_base, int p, int latent, int T,
-                               bool grad, hipStream_t s, LaunchTimer tm) {
-    return dispatch(0, dd, n_inst, count, q_base, p, latent, T, grad, 0, 0, 0, Launch{s, tm});
+                               bool grad, int loss, hipStream_t s, LaunchTimer tm) {
+    if (loss == kLossSammon) return launch_units_sammon(dd, n_inst, count, q_base, p, latent, T, grad, s, tm);
+    return units_dispatch<kLossRaw>(dd, n_inst, count, q_base, p, latent, T, grad, Launch{s, tm});
 }
 
 hipError_t launch_stress_reduce(const InstDesc* dd, int n_inst, int64_t blocks, int64_t q_base, int p, int latent,
                                 int T, int mode, int it, hipStream_t s, LaunchTimer tm) {
-    return dispatch(1, dd, n_inst, 0, q_base, p, latent, T, true, blocks, mode, it, Launch{s, tm});
+    const Launch L{s, tm};
+    if (T == 64) return reduce_dispatch_lat<64>(dd, n_inst, blocks, q_base, p, latent, mode, it, L);
+    if (T == 128) return reduce_dispatch_lat<128>(dd, n_inst, blocks, q_base, p, latent, mode, it, L);
+    return reduce_dispatch_lat<256>(dd, n_inst, blocks, q_base, p, latent, mode, it, L);
 }
 
 // Host mirror of reduce_blocks (must agree with the device functions above).
@@ -880,51 +64,30 @@ int64_t reduce_block_count(int64_t n, int64_t nb, int T) {
     return ns + (n + kNPT - 1) / kNPT;
 }
 
-
 hipError_t launch_fill_u32(uint32_t* ptr, int64_t count, uint32_t value, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, ptr, count, value);
     return hipGetLastError();
 }
 
-template <int P, int LAT, int T>
-static const void* persistent_fn() {
-    return reinterpret_cast<const void*>(&k_solve_persistent<P, LAT, T>);
+static const void* persistent_ptr(int p, int latent, int T, int loss) {
+    if (loss == kLossSammon) return persistent_ptr_sammon(p, latent, T);
+    return persistent_table<kLossRaw>(p, latent, T);
 }
 
-static const void* persistent_ptr(int p, int latent, int T) {
-#define GMDS_PT(LAT, TT)                                             \
-    switch (p_bucket(p)) {                                           \
-        case 1: return persistent_fn<1, LAT, TT>();                  \
-        case 2: return persistent_fn<2, LAT, TT>();                  \
-        case 3: return persistent_fn<3, LAT, TT>();                  \
-        case 4: return persistent_fn<4, LAT, TT>();                  \
-        default: return persistent_fn<kMaxP, LAT, TT>();             \
-    }
-    if (latent == 0) {
-        if (T == 64) { GMDS_PT(0, 64) }
-        if (T == 128) { GMDS_PT(0, 128) }
-        GMDS_PT(0, 256)
-    }
-    if (T == 64) { GMDS_PT(1, 64) }
-    if (T == 128) { GMDS_PT(1, 128) }
-    GMDS_PT(1, 256)
-#undef GMDS_PT
-}
-
-int persistent_max_blocks_per_cu(int p, int latent, int T) {
+int persistent_max_blocks_per_cu(int p, int latent, int T, int loss) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_ptr(p, latent, T), kWG, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_ptr(p, latent, T, loss), kWG, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
 hipError_t launch_solve_persistent(const InstDesc* dd, int n_inst, const int64_t* d_unit_prefix,
-                                   int64_t units_per_iter, int iters, int p, int latent, int T, int grid,
+                                   int64_t units_per_iter, int iters, int p, int latent, int T, int loss, int grid,
                                    SolveCtl* ctl, uint32_t* epochs, int64_t spin_limit, hipStream_t s,
                                    LaunchTimer tm) {
     if (iters <= 0 || units_per_iter <= 0) return hipSuccess;
-    const void* fn = persistent_ptr(p, latent, T);
+    const void* fn = persistent_ptr(p, latent, T, loss);
     void* args[] = {(void*)&dd, (void*)&n_inst, (void*)&d_unit_prefix, (void*)&units_per_iter, (void*)&iters,
                     (void*)&ctl, (void*)&epochs, (void*)&spin_limit};
     if (tm.start && tm.stop)

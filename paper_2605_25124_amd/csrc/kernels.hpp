@@ -9,6 +9,8 @@ namespace gmds {
 constexpr int kMaxP = 8;           // latent dimensions supported by the stress kernels
 constexpr int kMaxNu = 64;         // nu values per gini_dissim call
 constexpr int kStressWaves = 4;    // waves per stress workgroup (one stress partial each)
+constexpr int kLossRaw = 0;        // raw stress sum (delta - Delta)^2
+constexpr int kLossSammon = 1;     // Sammon stress sum (delta - Delta)^2 / Delta over sum Delta
 
 // Per-instance description of one stress evaluation / descent problem.
 // Built on the host, read by the kernels.
@@ -21,6 +23,7 @@ struct InstDesc {
     float* out_sigma;      // device (hi, lo), or nullptr
     const float* dsumsq;   // device (hi, lo) of sum_{i<j} Delta_ij^2 (Kruskal normaliser), or nullptr
     float* ks_hist;        // per-iteration Kruskal stress (descent only), or nullptr
+    const float* dsum;     // device (hi, lo) of sum_{i<j} Delta_ij (Sammon normaliser), or nullptr
     float* rowpart;        // scratch: [ntiles][T][pg] row partial gradients (one per row and tile)
     float* colpart;        // scratch: [ntiles][units][T][pg] column partial gradients (one per unit)
     float* sigpart;        // scratch: [ntiles][units][kStressWaves][2] partial stress (hi, lo) per wave
@@ -31,6 +34,7 @@ struct InstDesc {
     int64_t tile_off;      // first global work unit of this instance
     int64_t red_off;       // first block of this instance in a reduction launch
     int32_t p;
+    int32_t loss;          // kLossRaw or kLossSammon
     int32_t vec;           // Delta rows 16-byte aligned and ldd % 4 == 0
     float eta;             // descent step
     float c2;              // p = 2 Gini latent: 2^(1-nu)
@@ -79,7 +83,7 @@ hipError_t launch_dissim(const DissimArgs& a, hipStream_t s);
 // Stream global work units q_base .. q_base+count-1 of the n_inst instances
 // described by `dd` (device; sorted by tile_off): tile partials only.
 hipError_t launch_stress_units(const InstDesc* dd, int n_inst, int64_t count, int64_t q_base, int p, int latent, int T,
-                               bool grad, hipStream_t s, LaunchTimer tm = {});
+                               bool grad, int loss, hipStream_t s, LaunchTimer tm = {});
 // Reduce the partials of every instance; `blocks` is the sum over instances
 // of reduce_block_count (instances sorted by red_off); blocks are numbered
 // from q_base.  StressMode says what
@@ -90,17 +94,21 @@ int64_t reduce_block_count(int64_t n, int64_t nb, int T);
 int units_per_tile(int T);
 // One launch: all instances, all iterations of the descent.
 hipError_t launch_solve_persistent(const InstDesc* dd, int n_inst, const int64_t* d_unit_prefix,
-                                   int64_t units_per_iter, int iters, int p, int latent, int T, int grid,
+                                   int64_t units_per_iter, int iters, int p, int latent, int T, int loss, int grid,
                                    SolveCtl* ctl, uint32_t* epochs, int64_t spin_limit, hipStream_t s,
                                    LaunchTimer tm = {});
-int persistent_max_blocks_per_cu(int p, int latent, int T);
+int persistent_max_blocks_per_cu(int p, int latent, int T, int loss);
 // Set `count` words to `value` (counters, epochs).
 hipError_t launch_fill_u32(uint32_t* ptr, int64_t count, uint32_t value, hipStream_t s);
-// sum_{i<j} Delta_ij^2 of n_mat stacked matrices into out[2k], out[2k+1]
-// (hi, lo); `part` holds 2 * n_mat * sumsq_blocks(n) floats of scratch.
+// sum_{i<j} Delta_ij^power (power 1 or 2) of n_mat stacked matrices into
+// out[2k], out[2k+1] (hi, lo); `part` holds 2 * n_mat * sumsq_blocks(n) floats.
 int64_t sumsq_blocks(int64_t n);
+// max_i sum_{j != i, Delta_ij > 0} 1 / Delta_ij over full rows into out[0];
+// `part` holds rowinv_blocks(n) floats.
+int64_t rowinv_blocks(int64_t n);
+hipError_t launch_rowinv_max(const float* Delta, int64_t n, int64_t ldd, float* part, float* out, hipStream_t s);
 hipError_t launch_sumsq(const float* Delta, int64_t n, int64_t ldd, int n_mat, int64_t stride, float* part,
-                        float* out, hipStream_t s);
+                        float* out, int power, hipStream_t s);
 
 // Gradient components the stress kernels store per point in the tile
 // partials: the p = 2 Gini gradient is (-g, g), so one; p <= 4 has its own

@@ -21,6 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libginimds.so")
 GINI_OK = 0
 LATENT_GINI = 0
 LATENT_EUCLID = 1
+LOSS_RAW = 0
+LOSS_SAMMON = 1
 SOLVE_PERSISTENT = 1
 SOLVE_PLAIN = 2
 SOLVE_BATCHED = 4
@@ -39,11 +41,12 @@ class GiniError(RuntimeError):
 
 
 class _Instance(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int64), ("p", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+    _fields_ = [("n", ctypes.c_int64), ("p", ctypes.c_int32), ("loss", ctypes.c_int32),
                 ("Delta", ctypes.c_void_p), ("ldd", ctypes.c_int64), ("Z", ctypes.c_void_p),
                 ("ldz", ctypes.c_int64), ("nu", ctypes.c_double), ("latent", ctypes.c_int),
                 ("eta", ctypes.c_float), ("sigma_hist", ctypes.c_void_p),
-                ("delta_sumsq", ctypes.c_void_p), ("ks_hist", ctypes.c_void_p)]
+                ("delta_sumsq", ctypes.c_void_p), ("ks_hist", ctypes.c_void_p),
+                ("delta_sum", ctypes.c_void_p)]
 
 
 class _SelectOpts(ctypes.Structure):
@@ -81,6 +84,10 @@ def _load():
     L.gini_rank.argtypes = [P, P, i64, i32, i64, P, i64, P]
     L.gini_dissim.argtypes = [P, P, i64, i32, i64, P, i32, P, i64, i64, P]
     L.gini_sumsq.argtypes = [P, P, i64, i64, i32, i64, P, P]
+    L.gini_sum.argtypes = [P, P, i64, i64, i32, i64, P, P]
+    L.gini_sammon_fwd.argtypes = [P, P, i64, i64, P, P, i32, i64, f64, ctypes.c_int, P, P]
+    L.gini_sammon_bwd.argtypes = [P, P, i64, i64, P, P, i32, i64, f64, ctypes.c_int, P, P, i64, P, P]
+    L.gini_sammon_step.argtypes = [P, P, i64, i64, i32, f64, ctypes.c_int, ctypes.POINTER(f64), P]
     L.gini_stress_fwd.argtypes = [P, P, i64, i64, P, i32, i64, f64, ctypes.c_int, P, P]
     L.gini_stress_bwd.argtypes = [P, P, i64, i64, P, i32, i64, f64, ctypes.c_int, P, P, i64, P, P]
     L.gini_mds_solve.argtypes = [P, ctypes.POINTER(_Instance), i32, ctypes.POINTER(_Opts), P]
@@ -89,7 +96,8 @@ def _load():
                                  P, P, P, P]
     L.gini_profile_enable.argtypes = [P, ctypes.c_int]
     L.gini_profile_read.argtypes = [P, ctypes.POINTER(_Profile)]
-    for fn in ("gini_create", "gini_rank", "gini_dissim", "gini_sumsq", "gini_stress_fwd", "gini_stress_bwd",
+    for fn in ("gini_create", "gini_rank", "gini_dissim", "gini_sumsq", "gini_sum", "gini_sammon_fwd",
+               "gini_sammon_bwd", "gini_sammon_step", "gini_stress_fwd", "gini_stress_bwd",
                "gini_mds_solve", "gini_autotune", "gini_select_nu", "gini_profile_enable", "gini_profile_read"):
         getattr(L, fn).restype = ctypes.c_int
     return L
@@ -218,9 +226,9 @@ def gini_dissim(X: torch.Tensor, nus: Sequence[float], out: Optional[torch.Tenso
     return out
 
 
-def gini_sumsq(Delta: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """sum_{i<j} Delta_ij^2 of an n x n matrix or a (k, n, n) stack: a (k, 2)
-    device tensor of (hi, lo) pairs (k = 1 for a single matrix)."""
+def _sum_call(fn, Delta: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """A gini_sumsq-shaped call: (k, 2) device (hi, lo) pairs for an n x n
+    matrix (k = 1) or a (k, n, n) stack."""
     dev = _dev_index(Delta)
     D3 = Delta.unsqueeze(0) if Delta.dim() == 2 else Delta
     if D3.dim() != 3 or D3.shape[1] != D3.shape[2]:
@@ -234,8 +242,19 @@ def gini_sumsq(Delta: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch
     if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != 2 * k:
         raise ValueError("out must be a contiguous FP32 tensor of 2*k elements")
     c = context(dev)
-    c.check(_lib.gini_sumsq(c.handle, _ptr(D3), n, ldd, k, int(D3.stride(0)), _ptr(out), _stream(dev)))
+    c.check(fn(c.handle, _ptr(D3), n, ldd, k, int(D3.stride(0)), _ptr(out), _stream(dev)))
     return out
+
+
+def gini_sumsq(Delta: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """sum_{i<j} Delta_ij^2 (Kruskal normaliser) of an n x n matrix or a (k, n, n)
+    stack: a (k, 2) device tensor of (hi, lo) pairs."""
+    return _sum_call(_lib.gini_sumsq, Delta, out)
+
+
+def gini_sum(Delta: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """sum_{i<j} Delta_ij (Sammon normaliser), shaped as gini_sumsq."""
+    return _sum_call(_lib.gini_sum, Delta, out)
 
 
 def _check_pair(Delta: torch.Tensor, Z: torch.Tensor):
@@ -283,6 +302,65 @@ def gini_stress_bwd(Delta: torch.Tensor, Z: torch.Tensor, nu: float, latent: int
     return gradZ, out_sigma
 
 
+def _dsum(t: Optional[torch.Tensor], Delta: torch.Tensor) -> torch.Tensor:
+    if t is None:
+        return gini_sum(Delta)[0]
+    if t.dtype != torch.float32 or t.numel() < 2 or not t.is_contiguous():
+        raise ValueError("delta_sum must be a contiguous FP32 (hi, lo) pair")
+    return t
+
+
+def gini_sammon_fwd(Delta: torch.Tensor, Z: torch.Tensor, nu: float, latent: int = LATENT_GINI,
+                    delta_sum: Optional[torch.Tensor] = None, out_sigma: Optional[torch.Tensor] = None):
+    """Sammon stress (hi, lo); delta_sum from gini_sum (computed when omitted)."""
+    dev = _dev_index(Delta)
+    _check_pair(Delta, Z)
+    ldd = _mat(Delta, "Delta")
+    ldz = _mat(Z, "Z")
+    n, p = Z.shape
+    ds = _dsum(delta_sum, Delta)
+    if out_sigma is None:
+        out_sigma = torch.empty(2, dtype=torch.float32, device=Delta.device)
+    c = context(dev)
+    c.check(_lib.gini_sammon_fwd(c.handle, _ptr(Delta), n, ldd, _ptr(ds), _ptr(Z), p, ldz, float(nu), int(latent),
+                                 _ptr(out_sigma), _stream(dev)))
+    return out_sigma
+
+
+def gini_sammon_bwd(Delta: torch.Tensor, Z: torch.Tensor, nu: float, latent: int = LATENT_GINI,
+                    delta_sum: Optional[torch.Tensor] = None, grad_out: Optional[torch.Tensor] = None,
+                    gradZ: Optional[torch.Tensor] = None, out_sigma: Optional[torch.Tensor] = None):
+    """Gradient of the Sammon stress and the stress in one pass: (gradZ, sigma pair)."""
+    dev = _dev_index(Delta)
+    _check_pair(Delta, Z)
+    ldd = _mat(Delta, "Delta")
+    ldz = _mat(Z, "Z")
+    n, p = Z.shape
+    ds = _dsum(delta_sum, Delta)
+    if gradZ is None:
+        gradZ = torch.empty((n, p), dtype=torch.float32, device=Delta.device)
+    ldg = _mat(gradZ, "gradZ")
+    if out_sigma is None:
+        out_sigma = torch.empty(2, dtype=torch.float32, device=Delta.device)
+    if grad_out is not None and (grad_out.dtype != torch.float32 or grad_out.numel() != 1):
+        raise ValueError("grad_out must be a one-element FP32 tensor")
+    c = context(dev)
+    c.check(_lib.gini_sammon_bwd(c.handle, _ptr(Delta), n, ldd, _ptr(ds), _ptr(Z), p, ldz, float(nu), int(latent),
+                                 _ptr(grad_out), _ptr(gradZ), ldg, _ptr(out_sigma), _stream(dev)))
+    return gradZ, out_sigma
+
+
+def gini_sammon_step(Delta: torch.Tensor, p: int, nu: float, latent: int = LATENT_GINI) -> float:
+    """A descent step under which the Sammon stress does not increase."""
+    dev = _dev_index(Delta)
+    ldd = _mat(Delta, "Delta")
+    eta = ctypes.c_double(0.0)
+    c = context(dev)
+    c.check(_lib.gini_sammon_step(c.handle, _ptr(Delta), int(Delta.shape[0]), ldd, int(p), float(nu), int(latent),
+                                  ctypes.byref(eta), _stream(dev)))
+    return float(eta.value)
+
+
 @dataclass
 class Instance:
     """One descent problem for gini_mds_solve (Z is updated in place)."""
@@ -294,6 +372,8 @@ class Instance:
     sigma_hist: Optional[torch.Tensor] = None
     delta_sumsq: Optional[torch.Tensor] = None   # (hi, lo) from gini_sumsq; needed by ks_hist
     ks_hist: Optional[torch.Tensor] = None       # per-iteration Kruskal stress
+    loss: int = LOSS_RAW
+    delta_sum: Optional[torch.Tensor] = None     # (hi, lo) from gini_sum; needed by LOSS_SAMMON
 
 
 def _hist_ptr(t: Optional[torch.Tensor], name: str):
@@ -316,7 +396,10 @@ def _instances(insts: Sequence[Instance]):
         _check_pair(I.Delta, I.Z)
         a = arr[k]
         a.n, a.p = int(I.Z.shape[0]), int(I.Z.shape[1])
-        a.reserved0 = 0
+        a.loss = int(I.loss)
+        if I.delta_sum is not None and I.delta_sum.numel() < 2:
+            raise ValueError("delta_sum must hold (hi, lo)")
+        a.delta_sum = _hist_ptr(I.delta_sum, "delta_sum")
         a.Delta, a.ldd = I.Delta.data_ptr(), _mat(I.Delta, "Delta")
         a.Z, a.ldz = I.Z.data_ptr(), _mat(I.Z, "Z")
         a.nu, a.latent, a.eta = float(I.nu), int(I.latent), float(I.eta)
@@ -427,3 +510,25 @@ class GiniStress(torch.autograd.Function):
 
 def stress(Delta: torch.Tensor, Z: torch.Tensor, nu: float, latent: int = LATENT_GINI) -> torch.Tensor:
     return GiniStress.apply(Delta, Z, nu, latent)
+
+
+class GiniSammon(torch.autograd.Function):
+    """Sammon stress of Z against Delta with a hand-written backward (one pass
+    over Delta for the stress and its gradient, latent ranks held fixed)."""
+
+    @staticmethod
+    def forward(ctx, Delta, Z, nu, latent=LATENT_GINI, delta_sum=None):
+        if Z.requires_grad:
+            G, sig = gini_sammon_bwd(Delta, Z.detach(), nu, latent, delta_sum)
+            ctx.save_for_backward(G)
+        else:
+            sig = gini_sammon_fwd(Delta, Z, nu, latent, delta_sum)
+            ctx.save_for_backward(None)
+        return sig[0] + sig[1]
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (G,) = ctx.saved_tensors
+        if G is None:
+            return None, None, None, None, None
+        return None, G * grad_out, None, None, None

@@ -129,7 +129,7 @@ def test_solve_validation(gm):
 
     def inst(n=10, p=2, Z=0x2000, latent=0, nu=2.0, hist=None, res=0):
         a = Inst()
-        a.n, a.p, a.reserved0 = n, p, res
+        a.n, a.p, a.loss = n, p, res
         a.Delta, a.ldd, a.Z, a.ldz = 0x1000, n, Z, p
         a.nu, a.latent, a.eta, a.sigma_hist = nu, latent, 0.0, hist
         return a
@@ -147,6 +147,16 @@ def test_solve_validation(gm):
     assert "share Z" in _err(gm, h)
     assert run([inst(Z=0x2000, hist=0x5000), inst(Z=0x3000, hist=0x5000)], ok) == EINVAL
     assert run([inst(Z=0x2000, p=2), inst(Z=0x3000, p=3)], ok) == EUNSUPPORTED
+    sam = inst(res=1)                                       # Sammon loss
+    assert run([sam], ok) == EINVAL and "delta_sum" in _err(gm, h)
+    sam.delta_sum = 0x8000
+    assert run([sam], ok) == EINVAL and "eta" in _err(gm, h)
+    sam.eta = 0.5
+    sam.ks_hist, sam.delta_sumsq = 0x6000, 0x7000
+    assert run([sam], ok) == EINVAL and "raw stress" in _err(gm, h)
+    sam.ks_hist = None
+    raw = inst(Z=0x3000)
+    assert run([sam, raw], ok) == EUNSUPPORTED and "loss" in _err(gm, h)
     k = inst()
     k.ks_hist = 0x6000                                    # Kruskal history without its normaliser
     assert run([k], ok) == EINVAL
@@ -179,6 +189,24 @@ def test_sumsq_validation(gm):
         assert L.gini_sumsq(*args) == EINVAL, msg
         assert msg in _err(gm, h), (msg, _err(gm, h))
     assert L.gini_sumsq(None, D, 10, 10, 1, 0, out, None) == EINVAL
+    L.gini_destroy(h)
+
+
+def test_sammon_entry_validation(gm):
+    L, h = gm._lib, _ctx(gm)
+    D, Z, G, o, ds = (ctypes.c_void_p(v) for v in (0x1000, 0x2000, 0x3000, 0x4000, 0x5000))
+    assert L.gini_sammon_fwd(h, D, 10, 10, None, Z, 2, 2, 2.0, 0, o, None) == EINVAL
+    assert "delta_sum" in _err(gm, h)
+    assert L.gini_sammon_bwd(h, D, 10, 10, None, Z, 2, 2, 2.0, 0, None, G, 2, o, None) == EINVAL
+    assert L.gini_sammon_fwd(h, D, 1, 10, ds, Z, 2, 2, 2.0, 0, o, None) == EINVAL      # n < 2
+    assert L.gini_sammon_fwd(h, D, 10, 10, ds, Z, 1, 2, 2.0, 0, o, None) == EINVAL     # Gini latent, p = 1
+    eta = ctypes.c_double()
+    assert L.gini_sammon_step(h, D, 1, 1, 2, 2.0, 0, ctypes.byref(eta), None) == EINVAL
+    assert L.gini_sammon_step(h, D, 10, 9, 2, 2.0, 0, ctypes.byref(eta), None) == EINVAL
+    assert L.gini_sammon_step(h, D, 10, 10, 2, 0.9, 0, ctypes.byref(eta), None) == EINVAL
+    assert L.gini_sammon_step(h, D, 10, 10, 2, 2.0, 0, None, None) == EINVAL
+    assert L.gini_sum(h, D, 0, 4, 1, 0, o, None) == EINVAL
+    assert L.gini_sum(h, D, 10, 9, 1, 0, o, None) == EINVAL
     L.gini_destroy(h)
 
 

@@ -1,0 +1,111 @@
+"""GPU parity of the Sammon-stress path (Section IV-B) against the FP64 oracle:
+the normaliser, the fused stress + gradient, the safe step, and the descent."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2605_25124_amd import synth
+from tests._util import rel
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def gm():
+    from paper_2605_25124_amd import ginimds
+    return ginimds
+
+
+def _problem(gm, n, m, p, seed, nu=2.0, dup=True):
+    g = np.random.Generator(np.random.PCG64(seed))
+    X = g.standard_normal((n, m)).astype(np.float32)
+    if dup and n > 8:
+        X[5] = X[2]                                     # a zero dissimilarity
+    Z = (0.5 * g.standard_normal((n, p))).astype(np.float32)
+    D = gm.gini_dissim(torch.from_numpy(X).to(DEV), [nu])[0]
+    return D, torch.from_numpy(Z).to(DEV)
+
+
+@pytest.mark.parametrize("n", [2, 3, 64, 65, 513, 1000, 4097])
+def test_sum_parity(gm, n):
+    D, _ = _problem(gm, n, 5, 2, 900 + n)
+    s = gm.gini_sum(D)
+    ref = float(np.triu(D.cpu().numpy().astype(np.float64), 1).sum())
+    assert abs(float(s[0, 0].double() + s[0, 1].double()) - ref) <= 1e-6 * ref
+    assert torch.equal(s, gm.gini_sum(D))
+
+
+@pytest.mark.parametrize("n", [2, 3, 65, 513, 1000, 4097])
+@pytest.mark.parametrize("latent,p", [(0, 2), (0, 3), (1, 2)])
+def test_sammon_parity(gm, orc, n, latent, p):
+    nu = 2.0 if latent else 2.5
+    D, Z = _problem(gm, n, 6, p, 10 * n + p, nu=nu)
+    G, sig = gm.gini_sammon_bwd(D, Z, nu, latent)
+    s1 = gm.gini_sammon_fwd(D, Z, nu, latent)
+    s_ref, G_ref = orc.sammon(D.cpu().numpy(), Z.cpu().numpy(), nu, latent, orc.MATCH32)
+    for s in (sig, s1):
+        assert abs(float(s[0].double() + s[1].double()) - s_ref) <= 1e-4 * s_ref, (n, latent, p)
+    assert rel(G.cpu().numpy(), G_ref) <= 1e-4
+
+
+@pytest.mark.parametrize("latent,p", [(0, 2), (1, 2), (1, 3)])
+def test_sammon_step_matches_oracle(gm, orc, latent, p):
+    D, _ = _problem(gm, 700, 6, p, 31)
+    eta = gm.gini_sammon_step(D, p, 2.0, latent)
+    ref = orc.sammon_step(D.cpu().numpy(), p, 2.0, latent)
+    assert abs(eta - ref) <= 1e-5 * ref
+
+
+@pytest.mark.parametrize("latent,p", [(0, 2), (1, 2)])
+def test_sammon_descent(gm, orc, latent, p):
+    """Teacher-forced steps against the oracle, then a run that never rises,
+    and the three launch modes bitwise equal."""
+    w = synth.workload_small()
+    X = torch.from_numpy(w.X.astype(np.float32)).to(DEV)
+    D = gm.gini_dissim(X, [2.0])[0]
+    ds = gm.gini_sum(D)[0]
+    eta = gm.gini_sammon_step(D, p, 2.0, latent)
+    Dn = D.cpu().numpy()
+    Z = torch.from_numpy(w.Z0[0][:, :p].astype(np.float32).copy()).to(DEV)
+    for t in range(3):
+        Zt = Z.cpu().numpy()
+        h = torch.zeros(1, device=DEV)
+        gm.gini_mds_solve([gm.Instance(D, Z, 2.0, latent, eta, h, loss=gm.LOSS_SAMMON, delta_sum=ds)], 1,
+                          gm.SOLVE_BATCHED)
+        s_ref, G_ref = orc.sammon(Dn, Zt, 2.0, latent, orc.MATCH32)
+        assert abs(float(h[0]) - s_ref) <= 1e-4 * s_ref, t
+        step = (Zt.astype(np.float64) - Z.cpu().numpy().astype(np.float64)) / np.float32(eta)
+        assert rel(step, G_ref) <= 1e-4, t
+    runs = []
+    for flags in (gm.SOLVE_BATCHED, gm.SOLVE_PERSISTENT, gm.SOLVE_PLAIN):
+        Zr = torch.from_numpy(w.Z0[0][:, :p].astype(np.float32).copy()).to(DEV)
+        h = torch.zeros(80, device=DEV)
+        gm.gini_mds_solve([gm.Instance(D, Zr, 2.0, latent, eta, h, loss=gm.LOSS_SAMMON, delta_sum=ds)], 80, flags)
+        runs.append((Zr.cpu(), h.cpu()))
+    hist = runs[0][1].numpy().astype(np.float64)
+    assert np.all(np.diff(hist) <= 1e-5 * hist[0])
+    assert hist[-1] < 0.8 * hist[0]
+    for Zr, h in runs[1:]:
+        assert torch.equal(Zr, runs[0][0]) and torch.equal(h, runs[0][1])
+
+
+def test_sammon_autograd(gm, orc):
+    D, Z = _problem(gm, 300, 5, 2, 44)
+    Zr = Z.clone().requires_grad_(True)
+    loss = gm.GiniSammon.apply(D, Zr, 2.0, 0)
+    (2.0 * loss).backward()
+    G, s = gm.gini_sammon_bwd(D, Z, 2.0, 0)
+    assert torch.allclose(Zr.grad, 2.0 * G, rtol=1e-6, atol=0)
+    Dn = D.cpu().numpy().astype(np.float64)
+    Zn = Z.cpu().numpy().astype(np.float64)
+    h = 1e-6
+    Gn = G.cpu().numpy()
+    for i in (0, 2, 5, 299):
+        for c in range(2):
+            Zp, Zm = Zn.copy(), Zn.copy()
+            Zp[i, c] += h
+            Zm[i, c] -= h
+            fd = (orc.sammon(Dn, Zp, 2.0, 0, orc.EXACT, grad=False)[0]
+                  - orc.sammon(Dn, Zm, 2.0, 0, orc.EXACT, grad=False)[0]) / (2 * h)
+            assert abs(Gn[i, c] - fd) <= 1e-4 * np.abs(Gn).max(), (i, c)

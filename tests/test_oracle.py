@@ -384,3 +384,67 @@ def test_select_nu_scale_invariance_and_argmin(orc):
     assert best == best2 == int(np.argmin(ks.mean(axis=1)))
     np.testing.assert_allclose(mean, ks.mean(axis=1))
     assert np.all(np.isfinite(ks) & (ks > 0))
+
+
+# ------------------------------------------------------------ Sammon stress
+def test_sammon_two_points(orc):
+    """One pair: S = Delta, so the Sammon stress is (delta - Delta)^2 / Delta^2."""
+    D = np.array([[0.0, 2.5], [2.5, 0.0]])
+    Z = np.array([[0.0, 0.0], [3.0, 4.0]])
+    s, G = orc.sammon(D, Z, 2.0, orc.LATENT_EUCLID, orc.EXACT)
+    assert s == pytest.approx((5.0 - 2.5) ** 2 / 2.5 ** 2, rel=1e-15)
+    # d/dZ_0 of (|Z_0 - Z_1| - 2.5)^2 / 2.5^2 = 2 (5 - 2.5) / 2.5^2 * (Z_0 - Z_1) / 5
+    np.testing.assert_allclose(G[0], 2 * 2.5 / 6.25 * np.array([-3.0, -4.0]) / 5.0, rtol=1e-14)
+    np.testing.assert_allclose(G[1], -G[0], rtol=1e-15)
+
+
+def test_sammon_uniform_dissimilarities_scale_the_raw_stress(orc):
+    """All Delta_ij = c0: Sammon = raw / (c0 * S) with S = c0 * n (n - 1) / 2."""
+    n, c0 = 17, 1.7
+    D = np.full((n, n), c0)
+    np.fill_diagonal(D, 0.0)
+    Z = np.random.Generator(np.random.PCG64(5)).standard_normal((n, 2))
+    for latent in (orc.LATENT_EUCLID, orc.LATENT_GINI):
+        s, G = orc.sammon(D, Z, 2.5, latent, orc.EXACT)
+        r, Gr = orc.stress(D, Z, 2.5, latent, orc.EXACT)
+        scale = c0 * c0 * n * (n - 1) / 2
+        assert s == pytest.approx(r / scale, rel=1e-13)
+        np.testing.assert_allclose(G, Gr / scale, rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("latent,p,nu", [(0, 2, 2.0), (0, 3, 1.5), (1, 2, 2.0), (1, 3, 3.0)])
+def test_sammon_gradient_finite_difference(orc, latent, p, nu):
+    X, Z = _problem(13 + p, 16, 5, p)
+    X[3] = X[7]                                         # a zero dissimilarity: no weight, no NaN
+    D = orc.dissim(X, [nu], orc.EXACT)[0]
+    assert D[3, 7] == 0.0
+    s, G = orc.sammon(D, Z, nu, latent, orc.EXACT)
+    assert np.isfinite(s) and np.all(np.isfinite(G))
+    h = 1e-7
+    for i in (0, 3, 7, 15):
+        for c in range(p):
+            Zp, Zm = Z.copy(), Z.copy()
+            Zp[i, c] += h
+            Zm[i, c] -= h
+            fd = (orc.sammon(D, Zp, nu, latent, orc.EXACT, grad=False)[0]
+                  - orc.sammon(D, Zm, nu, latent, orc.EXACT, grad=False)[0]) / (2 * h)
+            assert fd == pytest.approx(G[i, c], rel=1e-5, abs=1e-8)
+
+
+@pytest.mark.parametrize("latent", [0, 1])
+def test_sammon_descent_never_increases(orc, latent):
+    """The Gershgorin step keeps the descent inside the majorising quadratic."""
+    w = synth.workload_small()
+    X = w.X[:80]
+    D = orc.dissim(X, [2.0], orc.EXACT)[0]
+    Z, hist = orc.solve_sammon(D, w.Z0[0][:80], 2.0, 60, latent, orc.EXACT)
+    assert np.all(np.diff(hist) <= 1e-12 * hist[0])
+    assert hist[-1] < 0.9 * hist[0]
+
+
+def test_sammon_zero_residual(orc):
+    g = np.random.Generator(np.random.PCG64(57))
+    X = g.standard_normal((20, 3))
+    D = orc.dissim(X, [1.7], orc.EXACT)[0]
+    s, G = orc.sammon(D, X, 1.7, orc.LATENT_GINI, orc.EXACT)
+    assert s == 0.0 and np.all(G == 0.0)
