@@ -316,6 +316,40 @@ gini_status gini_select_nu(gini_ctx* ctx, const float* X, int64_t n, int32_t m, 
                            float* Z_out, int64_t ldzo, int64_t stride_z, double* ks_mean, double* ks_fold,
                            int32_t* best, gini_stream_t stream);
 
+/* Options of gini_alternate_nu. */
+typedef struct {
+    int32_t iters;         /* Sammon descent steps per round, >= 1           */
+    int32_t p;             /* latent dimension                               */
+    gini_latent latent;    /* latent distance of the fit                     */
+    int32_t rounds;        /* alternations T >= 1                            */
+    int32_t init;          /* index in the nu list of the first nu fitted    */
+    int32_t flags;         /* launch mode, as gini_solve_opts.flags          */
+    int32_t tile;          /* 0 = library choice, else 64, 128 or 256        */
+} gini_alternate_opts;
+
+/*
+ * gini_alternate_nu -- the alternation of Algorithm 2 (Section V-C): starting
+ * from nu = nu[init] and the configuration Z0, every round
+ *   1. takes `iters` descent steps on the Sammon stress at the current nu,
+ *      from the configuration the previous round left (gini_sammon_step's
+ *      step for that nu's dissimilarities);
+ *   2. scores the configuration against every nu of the list by the Kruskal
+ *      stress with the Euclidean latent distance (no refit), and
+ *   3. moves to the nu with the smallest score.
+ * The dissimilarities of every nu come from one gini_dissim call (one
+ * ranking per pair) into the context's workspace (n_nu * n * ceil64(n)
+ * floats).  X: n x m FP32 (ldx >= m), n >= 2.  nu: HOST array of n_nu values
+ * (1 <= n_nu <= 64).  Z0, Z_out: n x p FP32 (ldz0, ldzo >= p); Z_out holds the
+ * last round's fit.  nu_hist: HOST int32[rounds], the index fitted in each
+ * round; ks: HOST double[rounds * n_nu] (round-major), the scores after each
+ * round's fit, or NULL; best: HOST int32, the argmin after the last round.
+ * Synchronises `stream`.
+ */
+gini_status gini_alternate_nu(gini_ctx* ctx, const float* X, int64_t n, int32_t m, int64_t ldx, const double* nu,
+                              int32_t n_nu, const float* Z0, int64_t ldz0, const gini_alternate_opts* opts,
+                              float* Z_out, int64_t ldzo, int32_t* nu_hist, double* ks, int32_t* best,
+                              gini_stream_t stream);
+
 /* Kernel timing collected by the context while profiling is enabled: HIP
  * events recorded on the launching stream around each stress-tile launch,
  * each reduction launch and each persistent launch. */

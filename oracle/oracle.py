@@ -218,6 +218,28 @@ def select_nu(X, nus, Z0, iters: int, folds: int = 1, latent: int = LATENT_GINI,
     return int(np.argmin(mean)), mean, ks, Zs
 
 
+def alternate_nu(X, nus, Z0, iters: int, rounds: int, init: int, latent: int = LATENT_GINI,
+                 mode: int = MATCH32):
+    """Algorithm 2's alternation: each round a Sammon fit at the current nu
+    (orc_sammon_step's step, warm start), then the Kruskal stress of the fit
+    against every nu with the Euclidean latent distance, and a move to the
+    argmin.  Returns (best index, nu index per round, ks[rounds, n_nu], Z)."""
+    Ds = dissim(np.asarray(X), list(nus), mode)
+    Z = np.asarray(Z0, dtype=np.float64).copy()
+    p = Z.shape[1]
+    cur = int(init)
+    hist = np.zeros(rounds, dtype=np.int64)
+    ks = np.zeros((rounds, len(nus)))
+    for t in range(rounds):
+        eta = sammon_step(Ds[cur], p, nus[cur], latent)
+        Z, _ = solve_sammon(Ds[cur], Z, nus[cur], iters, latent, mode, eta)
+        hist[t] = cur
+        for k, nu in enumerate(nus):
+            ks[t, k] = kruskal(Ds[k], Z, nu, LATENT_EUCLID, mode)
+        cur = int(np.argmin(ks[t]))
+    return cur, hist, ks, Z
+
+
 def grad_rows(Drows, rows, Z, nu: float, latent: int = LATENT_GINI, mode: int = MATCH32):
     """Gradient rows G[rows] from the corresponding rows of Delta; also returns
     the partial sum over the selected rows of sum_{j>i} r_ij^2."""

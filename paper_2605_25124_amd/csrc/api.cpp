@@ -1202,4 +1202,117 @@ gini_status gini_select_nu(gini_ctx* c, const float* X, int64_t n, int32_t m, in
     return GINI_OK;
 }
 
+gini_status gini_alternate_nu(gini_ctx* c, const float* X, int64_t n, int32_t m, int64_t ldx, const double* nu,
+                              int32_t n_nu, const float* Z0, int64_t ldz0, const gini_alternate_opts* o,
+                              float* Z_out, int64_t ldzo, int32_t* nu_hist, double* ks, int32_t* best,
+                              gini_stream_t stream) {
+    if (!c) return GINI_EINVAL;
+    c->err.clear();
+    if (!o) return fail(c, GINI_EINVAL, "opts must be non-null");
+    if (!X || !nu || !Z0 || !Z_out || !nu_hist || !best)
+        return fail(c, GINI_EINVAL, "X, nu, Z0, Z_out, nu_hist and best must be non-null");
+    if (n < 2) return fail(c, GINI_EINVAL, "n = %lld < 2", (long long)n);
+    if (m < 1 || m > kMaxDissimM) return fail(c, GINI_EINVAL, "m = %d outside 1..%d", m, kMaxDissimM);
+    if (ldx < m) return fail(c, GINI_EINVAL, "ldx = %lld < m = %d", (long long)ldx, m);
+    if (n_nu < 1 || n_nu > gmds::kMaxNu) return fail(c, GINI_EINVAL, "n_nu = %d outside 1..%d", n_nu, gmds::kMaxNu);
+    for (int k = 0; k < n_nu; ++k)
+        if (bad_nu(nu[k])) return fail(c, GINI_EINVAL, "nu[%d] must be finite and > 1", k);
+    if (o->iters < 1) return fail(c, GINI_EINVAL, "iters = %d < 1", o->iters);
+    if (o->rounds < 1) return fail(c, GINI_EINVAL, "rounds = %d < 1", o->rounds);
+    if (o->init < 0 || o->init >= n_nu) return fail(c, GINI_EINVAL, "init = %d outside 0..%d", o->init, n_nu - 1);
+    gini_status st = check_latent(c, o->p, nu[0], o->latent);
+    if (st != GINI_OK) return st;
+    const int p = o->p;
+    if (ldz0 < p || ldzo < p) return fail(c, GINI_EINVAL, "ldz0 and ldzo must be >= p = %d", p);
+    if (n > (int64_t)1 << 22) return fail(c, GINI_EUNSUPPORTED, "n > 2^22 is not supported");
+    gini_solve_opts so{o->iters, o->flags, o->tile, 0};
+    st = check_opts(c, &so);
+    if (st != GINI_OK) return st;
+    st = ensure_ready(c);
+    if (st != GINI_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+
+    // workspace: the n_nu matrices, then per nu (sum, sum of squares, Euclidean stress) as (hi, lo)
+    const int64_t ld = (n + 63) / 64 * 64;
+    const size_t mat = (size_t)n * ld;
+    const size_t aux = (size_t)n_nu * mat;
+    st = ensure_select(c, (aux + 6 * (size_t)n_nu) * sizeof(float));
+    if (st != GINI_OK) return st;
+    float* ws = c->sel;
+    float* dsum = ws + aux;
+    float* dsq = dsum + 2 * (size_t)n_nu;
+    float* sig = dsq + 2 * (size_t)n_nu;
+    st = gini_dissim(c, X, n, m, ldx, nu, n_nu, ws, ld, (int64_t)mat, stream);
+    if (st != GINI_OK) return st;
+    st = gini_sum(c, ws, n, ld, n_nu, (int64_t)mat, dsum, stream);
+    if (st != GINI_OK) return st;
+    st = gini_sumsq(c, ws, n, ld, n_nu, (int64_t)mat, dsq, stream);
+    if (st != GINI_OK) return st;
+    GINI_HIP(c, hipMemcpy2DAsync(Z_out, (size_t)ldzo * sizeof(float), Z0, (size_t)ldz0 * sizeof(float),
+                                 (size_t)p * sizeof(float), (size_t)n, hipMemcpyDeviceToDevice, s));
+    std::vector<float> hsq(2 * (size_t)n_nu);
+    GINI_HIP(c, hipMemcpyAsync(hsq.data(), dsq, hsq.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    GINI_HIP(c, hipStreamSynchronize(s));
+    std::vector<double> eta(n_nu, 0.0);
+    std::vector<gini_instance> ev(n_nu);
+    for (int k = 0; k < n_nu; ++k) {
+        gini_instance& I = ev[k];
+        I = gini_instance{};
+        I.n = n;
+        I.p = p;
+        I.Delta = ws + (size_t)k * mat;
+        I.ldd = ld;
+        I.Z = Z_out;
+        I.ldz = ldzo;
+        I.nu = nu[k];
+        I.latent = GINI_LATENT_EUCLID;
+    }
+    int cur = o->init;
+    std::vector<float> hs(2 * (size_t)n_nu);
+    for (int t = 0; t < o->rounds; ++t) {
+        // 1. Sammon fit at the current nu, warm-started
+        if (eta[cur] <= 0.0) {
+            st = gini_sammon_step(c, ws + (size_t)cur * mat, n, ld, p, nu[cur], o->latent, &eta[cur], stream);
+            if (st != GINI_OK) return st;
+            if (!(eta[cur] > 0.0)) return fail(c, GINI_EINVAL, "nu[%d]: every dissimilarity is zero", cur);
+        }
+        gini_instance fit{};
+        fit.n = n;
+        fit.p = p;
+        fit.loss = GINI_LOSS_SAMMON;
+        fit.Delta = ws + (size_t)cur * mat;
+        fit.ldd = ld;
+        fit.Z = Z_out;
+        fit.ldz = ldzo;
+        fit.nu = nu[cur];
+        fit.latent = o->latent;
+        fit.eta = (float)eta[cur];
+        fit.delta_sum = dsum + 2 * (size_t)cur;
+        st = solve_impl(c, &fit, 1, &so, s);
+        if (st != GINI_OK) return st;
+        nu_hist[t] = cur;
+        // 2. Kruskal stress of the fit against every nu, Euclidean latent distance
+        st = eval_sigma_batch(c, ev.data(), n_nu, pick_tile(n), sig, s);
+        if (st != GINI_OK) return st;
+        GINI_HIP(c, hipMemcpyAsync(hs.data(), sig, hs.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+        GINI_HIP(c, hipStreamSynchronize(s));
+        // 3. move to the argmin
+        int bi = 0;
+        double bv = 0.0;
+        for (int k = 0; k < n_nu; ++k) {
+            const double den = (double)hsq[2 * k] + (double)hsq[2 * k + 1];
+            const double v = den > 0.0 ? std::sqrt(((double)hs[2 * k] + (double)hs[2 * k + 1]) / den) : 0.0;
+            if (!std::isfinite(v)) return fail(c, GINI_ENOTFINITE, "round %d: Kruskal stress of nu[%d] is not finite", t, k);
+            if (ks) ks[(size_t)t * n_nu + k] = v;
+            if (k == 0 || v < bv) {
+                bv = v;
+                bi = k;
+            }
+        }
+        cur = bi;
+    }
+    *best = cur;
+    return GINI_OK;
+}
+
 }  // extern "C"

@@ -54,6 +54,12 @@ class _SelectOpts(ctypes.Structure):
                 ("folds", ctypes.c_int32), ("flags", ctypes.c_int32), ("tile", ctypes.c_int32)]
 
 
+class _AlternateOpts(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("p", ctypes.c_int32), ("latent", ctypes.c_int),
+                ("rounds", ctypes.c_int32), ("init", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("tile", ctypes.c_int32)]
+
+
 class _Profile(ctypes.Structure):
     _fields_ = [("tile_launches", ctypes.c_int64), ("tile_ms", ctypes.c_double),
                 ("reduce_launches", ctypes.c_int64), ("reduce_ms", ctypes.c_double),
@@ -94,11 +100,14 @@ def _load():
     L.gini_autotune.argtypes = [P, ctypes.POINTER(_Instance), i32, i32, ctypes.POINTER(_Opts), P]
     L.gini_select_nu.argtypes = [P, P, i64, i32, i64, P, i32, P, i64, ctypes.POINTER(_SelectOpts), P, i64, i64,
                                  P, P, P, P]
+    L.gini_alternate_nu.argtypes = [P, P, i64, i32, i64, P, i32, P, i64, ctypes.POINTER(_AlternateOpts), P, i64,
+                                    P, P, P, P]
     L.gini_profile_enable.argtypes = [P, ctypes.c_int]
     L.gini_profile_read.argtypes = [P, ctypes.POINTER(_Profile)]
     for fn in ("gini_create", "gini_rank", "gini_dissim", "gini_sumsq", "gini_sum", "gini_sammon_fwd",
                "gini_sammon_bwd", "gini_sammon_step", "gini_stress_fwd", "gini_stress_bwd",
-               "gini_mds_solve", "gini_autotune", "gini_select_nu", "gini_profile_enable", "gini_profile_read"):
+               "gini_mds_solve", "gini_autotune", "gini_select_nu", "gini_alternate_nu", "gini_profile_enable",
+               "gini_profile_read"):
         getattr(L, fn).restype = ctypes.c_int
     return L
 
@@ -468,6 +477,41 @@ def gini_select_nu(X: torch.Tensor, nus: Sequence[float], Z0: torch.Tensor, iter
                                 _ptr(Z_out), ldzo, int(Z_out.stride(0)), ctypes.c_void_p(ks_mean.ctypes.data),
                                 ctypes.c_void_p(ks_fold.ctypes.data), ctypes.byref(best), _stream(dev)))
     return int(best.value), ks_mean, ks_fold, Z_out
+
+
+def gini_alternate_nu(X: torch.Tensor, nus: Sequence[float], Z0: torch.Tensor, iters: int, rounds: int = 3,
+                      init: Optional[int] = None, latent: int = LATENT_GINI, flags: int = SOLVE_BATCHED,
+                      tile: int = 0, Z_out: Optional[torch.Tensor] = None):
+    """Algorithm 2's alternation: Sammon fit at the current nu, then move to the
+    nu whose dissimilarities the fit matches best (Kruskal stress, Euclidean
+    latent distance).  init defaults to the index of nu = 2 (else 0).  Returns
+    (best index, nu index fitted per round, ks[rounds, n_nu], Z_out)."""
+    import numpy as np
+    dev = _dev_index(X)
+    if _dev_index(Z0) != dev:
+        raise ValueError("X and Z0 must live on one device")
+    ldx = _mat(X, "X")
+    ldz0 = _mat(Z0, "Z0")
+    n, m = X.shape
+    if Z0.shape[0] != n:
+        raise ValueError("Z0 must have the rows of X")
+    p = int(Z0.shape[1])
+    k = len(nus)
+    if init is None:
+        init = [float(v) for v in nus].index(2.0) if 2.0 in [float(v) for v in nus] else 0
+    if Z_out is None:
+        Z_out = torch.empty((n, p), dtype=torch.float32, device=X.device)
+    ldzo = _mat(Z_out, "Z_out")
+    nus_h = (ctypes.c_double * k)(*[float(v) for v in nus])
+    hist = np.zeros(int(rounds), dtype=np.int32)
+    ks = np.zeros((int(rounds), k), dtype=np.float64)
+    best = ctypes.c_int32(-1)
+    opts = _AlternateOpts(int(iters), p, int(latent), int(rounds), int(init), int(flags), int(tile))
+    c = context(dev)
+    c.check(_lib.gini_alternate_nu(c.handle, _ptr(X), n, m, ldx, nus_h, k, _ptr(Z0), ldz0, ctypes.byref(opts),
+                                   _ptr(Z_out), ldzo, ctypes.c_void_p(hist.ctypes.data),
+                                   ctypes.c_void_p(ks.ctypes.data), ctypes.byref(best), _stream(dev)))
+    return int(best.value), hist, ks, Z_out
 
 
 def gini_profile_enable(device: int = 0, enable: bool = True) -> None:

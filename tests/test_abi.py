@@ -210,6 +210,28 @@ def test_sammon_entry_validation(gm):
     L.gini_destroy(h)
 
 
+def test_alternate_validation(gm):
+    L, h = gm._lib, _ctx(gm)
+    X, Z0, Zo = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    nu = (ctypes.c_double * 2)(2.0, 3.0)
+    hist = (ctypes.c_int32 * 3)()
+    best = ctypes.c_int32()
+
+    def run(n=100, opts=None, Zout=Zo, nus=nu):
+        o = opts or gm._AlternateOpts(10, 2, 0, 3, 0, gm.SOLVE_BATCHED, 0)
+        return L.gini_alternate_nu(h, X, n, 4, 4, nus, 2, Z0, 2, ctypes.byref(o), Zout, 2, hist, None,
+                                   ctypes.byref(best), None)
+
+    assert run(n=1) == EINVAL
+    assert run(opts=gm._AlternateOpts(0, 2, 0, 3, 0, gm.SOLVE_BATCHED, 0)) == EINVAL and "iters" in _err(gm, h)
+    assert run(opts=gm._AlternateOpts(10, 2, 0, 0, 0, gm.SOLVE_BATCHED, 0)) == EINVAL and "rounds" in _err(gm, h)
+    assert run(opts=gm._AlternateOpts(10, 2, 0, 3, 2, gm.SOLVE_BATCHED, 0)) == EINVAL and "init" in _err(gm, h)
+    assert run(opts=gm._AlternateOpts(10, 1, 0, 3, 0, gm.SOLVE_BATCHED, 0)) == EINVAL
+    assert run(Zout=None) == EINVAL
+    assert run(nus=(ctypes.c_double * 2)(2.0, 1.0)) == EINVAL
+    L.gini_destroy(h)
+
+
 def test_select_validation(gm):
     L, h = gm._lib, _ctx(gm)
     X, Z0, Zo = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)

@@ -448,3 +448,30 @@ def test_sammon_zero_residual(orc):
     D = orc.dissim(X, [1.7], orc.EXACT)[0]
     s, G = orc.sammon(D, X, 1.7, orc.LATENT_GINI, orc.EXACT)
     assert s == 0.0 and np.all(G == 0.0)
+
+
+# ------------------------------------------------ Algorithm 2 (alternation)
+def test_alternation_on_one_dimensional_data(orc):
+    """Two-coordinate rows: Delta_nu = (1/2)^(nu-1) |y_i - y_j| embeds in one
+    dimension, the Sammon fit at nu reaches it, and the Kruskal stress of that
+    fit against nu' is |2^(nu' - nu) - 1|: the alternation stays at nu."""
+    g = np.random.Generator(np.random.PCG64(71))
+    X = g.standard_normal((40, 2))
+    Z0 = X[:, :1] - X[:, 1:]                       # right order, wrong scale
+    nus = [1.5, 2.0, 3.0]
+    best, hist, ks, Z = orc.alternate_nu(X, nus, Z0, 1500, 2, 2, orc.LATENT_EUCLID, orc.EXACT)
+    assert list(hist) == [2, 2] and best == 2
+    ref = [abs(2.0 ** (v - 3.0) - 1.0) for v in nus]
+    np.testing.assert_allclose(ks[-1], ref, atol=2e-3)
+
+
+def test_alternation_scale_invariance(orc):
+    w = synth.workload_small()
+    X, Z0 = w.X[:50], w.Z0[0][:50].astype(np.float64)
+    nus = [1.5, 2.0, 3.0]
+    b1, h1, k1, Z1 = orc.alternate_nu(X, nus, Z0, 30, 3, 1, orc.LATENT_GINI, orc.EXACT)
+    b2, h2, k2, Z2 = orc.alternate_nu(3.0 * X, nus, 3.0 * Z0, 30, 3, 1, orc.LATENT_GINI, orc.EXACT)
+    assert list(h1) == list(h2) and b1 == b2
+    np.testing.assert_allclose(k2, k1, rtol=1e-9)
+    np.testing.assert_allclose(Z2, 3.0 * Z1, rtol=1e-9, atol=1e-12)
+    assert h1[0] == 1 and all(h1[t + 1] == int(np.argmin(k1[t])) for t in range(2))
