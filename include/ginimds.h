@@ -350,6 +350,25 @@ gini_status gini_alternate_nu(gini_ctx* ctx, const float* X, int64_t n, int32_t 
                               float* Z_out, int64_t ldzo, int32_t* nu_hist, double* ks, int32_t* best,
                               gini_stream_t stream);
 
+/*
+ * gini_classical_mds -- classical MDS (Section IV-A) of a dissimilarity
+ * matrix, e.g. as the starting configuration of the descent: the p
+ * eigenpairs of B = -1/2 H D^2 H (D^2 the entrywise squares of Delta,
+ * H = I - 11^T/n) with the largest eigenvalues, Z = V_p diag(sqrt(max(lam, 0))).
+ * B is never formed: subspace iteration on a block of q = min(8, p + 4, n - 1)
+ * centred vectors applies it as one pass over the rows of Delta (both
+ * triangles read, diagonal skipped), with a Rayleigh-Ritz step per iteration;
+ * it stops when the p largest Ritz values move by at most tol of the largest
+ * (or after max_iters).  The start block is fixed, so results repeat.
+ * Delta: n x n FP32 (ldd >= n), n >= 2.  1 <= p <= min(8, n - 1).  Z: n x p
+ * FP32 (ldz >= p), device.  eigvals: HOST double[p] (decreasing) or NULL;
+ * iters_done: HOST int32 or NULL.  The columns of Z are determined up to sign.
+ * Uses the context's workspace; synchronises `stream`.
+ */
+gini_status gini_classical_mds(gini_ctx* ctx, const float* Delta, int64_t n, int64_t ldd, int32_t p,
+                               int32_t max_iters, double tol, float* Z, int64_t ldz, double* eigvals,
+                               int32_t* iters_done, gini_stream_t stream);
+
 /* Kernel timing collected by the context while profiling is enabled: HIP
  * events recorded on the launching stream around each stress-tile launch,
  * each reduction launch and each persistent launch. */

@@ -240,6 +240,22 @@ def alternate_nu(X, nus, Z0, iters: int, rounds: int, init: int, latent: int = L
     return cur, hist, ks, Z
 
 
+def classical_mds(Delta, p: int):
+    """Section IV-A: B = -1/2 H D^2 H, its p largest eigenpairs (LAPACK's
+    symmetric eigensolver as the library step), Z = V_p sqrt(max(lam, 0)).
+    Returns (Z, eigenvalues in decreasing order)."""
+    D = _f64(Delta)
+    n = D.shape[0]
+    D2 = D * D
+    np.fill_diagonal(D2, 0.0)
+    H = np.eye(n) - np.ones((n, n)) / n
+    B = -0.5 * H @ D2 @ H
+    lam, V = np.linalg.eigh(0.5 * (B + B.T))
+    order = np.argsort(lam)[::-1][:p]
+    lam = lam[order]
+    return V[:, order] * np.sqrt(np.maximum(lam, 0.0)), lam
+
+
 def grad_rows(Drows, rows, Z, nu: float, latent: int = LATENT_GINI, mode: int = MATCH32):
     """Gradient rows G[rows] from the corresponding rows of Delta; also returns
     the partial sum over the selected rows of sum_{j>i} r_ij^2."""

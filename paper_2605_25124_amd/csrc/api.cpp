@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <numeric>
 #include <string>
@@ -224,6 +225,48 @@ gini_status ensure_scratch(gini_ctx* c, size_t bytes) {
         return fail(c, GINI_ENOMEM, "scratch allocation of %zu bytes failed", cap);
     c->scratch_bytes = cap;
     return GINI_OK;
+}
+
+// Symmetric eigen-decomposition of a small q x q matrix A (row-major, FP64)
+// by cyclic Jacobi rotations: A = W diag(lam) W^T, columns of W the vectors.
+void jacobi_eig(int q, std::vector<double> A, std::vector<double>& lam, std::vector<double>& W) {
+    W.assign((size_t)q * q, 0.0);
+    for (int i = 0; i < q; ++i) W[(size_t)i * q + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < q; ++i)
+            for (int j = 0; j < q; ++j) {
+                tot += A[(size_t)i * q + j] * A[(size_t)i * q + j];
+                if (i != j) off += A[(size_t)i * q + j] * A[(size_t)i * q + j];
+            }
+        if (off <= 1e-30 * tot || off == 0.0) break;
+        for (int pp = 0; pp < q - 1; ++pp)
+            for (int qq = pp + 1; qq < q; ++qq) {
+                const double apq = A[(size_t)pp * q + qq];
+                if (apq == 0.0) continue;
+                const double app = A[(size_t)pp * q + pp], aqq = A[(size_t)qq * q + qq];
+                const double theta = 0.5 * (aqq - app) / apq;
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < q; ++k) {        // A <- J^T A J
+                    const double akp = A[(size_t)k * q + pp], akq = A[(size_t)k * q + qq];
+                    A[(size_t)k * q + pp] = cs * akp - sn * akq;
+                    A[(size_t)k * q + qq] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < q; ++k) {
+                    const double apk = A[(size_t)pp * q + k], aqk = A[(size_t)qq * q + k];
+                    A[(size_t)pp * q + k] = cs * apk - sn * aqk;
+                    A[(size_t)qq * q + k] = sn * apk + cs * aqk;
+                }
+                for (int k = 0; k < q; ++k) {
+                    const double wkp = W[(size_t)k * q + pp], wkq = W[(size_t)k * q + qq];
+                    W[(size_t)k * q + pp] = cs * wkp - sn * wkq;
+                    W[(size_t)k * q + qq] = sn * wkp + cs * wkq;
+                }
+            }
+    }
+    lam.resize(q);
+    for (int i = 0; i < q; ++i) lam[i] = A[(size_t)i * q + i];
 }
 
 gini_status ensure_select(gini_ctx* c, size_t bytes) {
@@ -1312,6 +1355,165 @@ gini_status gini_alternate_nu(gini_ctx* c, const float* X, int64_t n, int32_t m,
         cur = bi;
     }
     *best = cur;
+    return GINI_OK;
+}
+
+gini_status gini_classical_mds(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, int32_t p, int32_t max_iters,
+                               double tol, float* Z, int64_t ldz, double* eigvals, int32_t* iters_done,
+                               gini_stream_t stream) {
+    if (!c) return GINI_EINVAL;
+    c->err.clear();
+    if (!Delta || !Z) return fail(c, GINI_EINVAL, "Delta and Z must be non-null");
+    if (n < 2) return fail(c, GINI_EINVAL, "n = %lld < 2", (long long)n);
+    if (ldd < n) return fail(c, GINI_EINVAL, "ldd = %lld < n = %lld", (long long)ldd, (long long)n);
+    if (p < 1 || p > gmds::kMaxCmdsQ || p > n - 1)
+        return fail(c, GINI_EINVAL, "p = %d outside 1..min(%d, n-1)", p, gmds::kMaxCmdsQ);
+    if (ldz < p) return fail(c, GINI_EINVAL, "ldz = %lld < p = %d", (long long)ldz, p);
+    if (max_iters < 1) return fail(c, GINI_EINVAL, "max_iters = %d < 1", max_iters);
+    if (!(tol >= 0.0)) return fail(c, GINI_EINVAL, "tol must be >= 0");
+    if (n > (int64_t)1 << 31) return fail(c, GINI_EUNSUPPORTED, "n too large");
+    gini_status st = ensure_ready(c);
+    if (st != GINI_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int q = (int)std::min<int64_t>({(int64_t)gmds::kMaxCmdsQ, (int64_t)p + 4, n - 1});
+    const int Q = gmds::kMaxCmdsQ;
+    // workspace: V, Y' (D^2 V), Yh (B V), then small buffers
+    const size_t nq = (size_t)n * q;
+    const size_t small = 2 * (size_t)Q * Q + 2 * (size_t)Q * Q + Q;
+    const size_t parts = 2 * (size_t)Q * Q * gmds::gram_blocks(n);
+    st = ensure_select(c, (3 * nq + small + parts + 64) * sizeof(float));
+    if (st != GINI_OK) return st;
+    float* V = c->sel;
+    float* Yp = V + nq;
+    float* Yh = Yp + nq;
+    float* gout = Yh + nq;                     // Q*Q (hi, lo)
+    float* Mdev = gout + 2 * (size_t)Q * Q;    // Q*Q
+    float* Idev = Mdev + (size_t)Q * Q;        // Q*Q identity (q x q)
+    float* shift = Idev + (size_t)Q * Q;       // Q
+    float* part = shift + Q;
+    std::vector<float> hg(2 * (size_t)Q * Q), hm((size_t)Q * Q);
+    auto fetch = [&](int ne, std::vector<double>& out) -> gini_status {
+        GINI_HIP(c, hipMemcpyAsync(hg.data(), gout, 2 * (size_t)ne * sizeof(float), hipMemcpyDeviceToHost, s));
+        GINI_HIP(c, hipStreamSynchronize(s));
+        out.resize(ne);
+        for (int e = 0; e < ne; ++e) out[e] = (double)hg[2 * e] + (double)hg[2 * e + 1];
+        return GINI_OK;
+    };
+    auto put = [&](float* dst, const std::vector<double>& v) -> gini_status {
+        for (size_t k = 0; k < v.size(); ++k) hm[k] = (float)v[k];
+        GINI_HIP(c, hipMemcpyAsync(dst, hm.data(), v.size() * sizeof(float), hipMemcpyHostToDevice, s));
+        GINI_HIP(c, hipStreamSynchronize(s));      // hm is reused at once
+        return GINI_OK;
+    };
+    // Orthonormalise the centred block A (n x q) into V: eigen-decompose its
+    // Gram matrix G = W S W^T and map V = A W S^(-1/2); directions with
+    // S below 1e-12 of the largest become zero columns (a rank-deficient B).
+    auto orthonormalise = [&](const float* A) -> gini_status {
+        GINI_HIP(c, gmds::launch_gram(A, q, A, q, n, part, gout, s));
+        std::vector<double> G, lam, W;
+        gini_status e = fetch(q * q, G);
+        if (e != GINI_OK) return e;
+        for (int i = 0; i < q; ++i)
+            for (int j = 0; j < i; ++j) G[(size_t)i * q + j] = G[(size_t)j * q + i] = 0.5 * (G[(size_t)i * q + j] + G[(size_t)j * q + i]);
+        jacobi_eig(q, G, lam, W);
+        double mx = 0.0;
+        for (double v : lam) mx = std::max(mx, v);
+        std::vector<double> M((size_t)q * q, 0.0);
+        for (int k = 0; k < q; ++k) {
+            if (!(lam[k] > 1e-12 * mx) || !(mx > 0.0)) continue;
+            const double sc = 1.0 / std::sqrt(lam[k]);
+            for (int i = 0; i < q; ++i) M[(size_t)i * q + k] = W[(size_t)i * q + k] * sc;
+        }
+        e = put(Mdev, M);
+        if (e != GINI_OK) return e;
+        GINI_HIP(c, gmds::launch_rowmat(A, q, nullptr, 1.f, Mdev, q, n, V, q, s));
+        return GINI_OK;
+    };
+    // start: a fixed pseudo-random block (xorshift64*), centred
+    {
+        std::vector<float> v0(nq);
+        uint64_t x = 0x9E3779B97F4A7C15ull;
+        for (size_t k = 0; k < nq; ++k) {
+            x ^= x >> 12;
+            x ^= x << 25;
+            x ^= x >> 27;
+            v0[k] = (float)((double)((x * 0x2545F4914F6CDD1Dull) >> 11) * (1.0 / 9007199254740992.0) - 0.5);
+        }
+        GINI_HIP(c, hipMemcpyAsync(Yp, v0.data(), nq * sizeof(float), hipMemcpyHostToDevice, s));
+        GINI_HIP(c, gmds::launch_gram(Yp, q, nullptr, 1, n, part, gout, s));
+        std::vector<double> cs;
+        st = fetch(q, cs);
+        if (st != GINI_OK) return st;
+        for (auto& v : cs) v /= (double)n;
+        st = put(shift, cs);
+        if (st != GINI_OK) return st;
+        std::vector<double> I((size_t)q * q, 0.0);
+        for (int i = 0; i < q; ++i) I[(size_t)i * q + i] = 1.0;
+        st = put(Idev, I);
+        if (st != GINI_OK) return st;
+        GINI_HIP(c, gmds::launch_rowmat(Yp, q, shift, 1.f, Idev, q, n, Yh, q, s));
+        st = orthonormalise(Yh);
+        if (st != GINI_OK) return st;
+    }
+    std::vector<double> lam, W, prev;
+    int it = 0;
+    for (; it < max_iters; ++it) {
+        // Yh = B V = -1/2 H (D^2 V)
+        GINI_HIP(c, gmds::launch_d2v(Delta, n, ldd, V, q, Yp, s));
+        GINI_HIP(c, gmds::launch_gram(Yp, q, nullptr, 1, n, part, gout, s));
+        std::vector<double> cs;
+        st = fetch(q, cs);
+        if (st != GINI_OK) return st;
+        for (auto& v : cs) v /= (double)n;
+        st = put(shift, cs);
+        if (st != GINI_OK) return st;
+        GINI_HIP(c, gmds::launch_rowmat(Yp, q, shift, -0.5f, Idev, q, n, Yh, q, s));
+        // Rayleigh-Ritz on span(V): T = V^T B V
+        GINI_HIP(c, gmds::launch_gram(V, q, Yh, q, n, part, gout, s));
+        std::vector<double> T;
+        st = fetch(q * q, T);
+        if (st != GINI_OK) return st;
+        for (int i = 0; i < q; ++i)
+            for (int j = 0; j < i; ++j) T[(size_t)i * q + j] = T[(size_t)j * q + i] = 0.5 * (T[(size_t)i * q + j] + T[(size_t)j * q + i]);
+        jacobi_eig(q, T, lam, W);
+        std::vector<double> top(lam);
+        std::sort(top.begin(), top.end(), std::greater<double>());
+        top.resize(p);
+        bool done = false;
+        if (!prev.empty()) {
+            double scale = 0.0, diff = 0.0;
+            for (int k = 0; k < p; ++k) {
+                scale = std::max(scale, std::fabs(top[k]));
+                diff = std::max(diff, std::fabs(top[k] - prev[k]));
+            }
+            done = diff <= tol * scale;
+        }
+        prev = top;
+        if (done) {
+            ++it;
+            break;
+        }
+        st = orthonormalise(Yh);                   // V <- orth(B V)
+        if (st != GINI_OK) return st;
+    }
+    // the p Ritz pairs with the largest eigenvalues: Z = V W_p diag(sqrt(max(lam, 0)))
+    std::vector<int> idx(q);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a2, int b2) { return lam[a2] > lam[b2]; });
+    std::vector<double> M((size_t)q * p, 0.0);
+    for (int k = 0; k < p; ++k) {
+        const int j = idx[k];
+        const double sc = std::sqrt(std::max(lam[j], 0.0));
+        for (int i = 0; i < q; ++i) M[(size_t)i * p + k] = W[(size_t)i * q + j] * sc;
+        if (eigvals) eigvals[k] = lam[j];
+    }
+    st = put(Mdev, M);
+    if (st != GINI_OK) return st;
+    GINI_HIP(c, gmds::launch_rowmat(V, q, nullptr, 1.f, Mdev, p, n, Z, ldz, s));
+    GINI_HIP(c, hipStreamSynchronize(s));
+    if (iters_done) *iters_done = it;
+    for (int k = 0; k < p; ++k)
+        if (eigvals && !std::isfinite(eigvals[k])) return fail(c, GINI_ENOTFINITE, "eigenvalue %d is not finite", k);
     return GINI_OK;
 }
 

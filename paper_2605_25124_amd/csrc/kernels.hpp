@@ -9,6 +9,7 @@ namespace gmds {
 constexpr int kMaxP = 8;           // latent dimensions supported by the stress kernels
 constexpr int kMaxNu = 64;         // nu values per gini_dissim call
 constexpr int kStressWaves = 4;    // waves per stress workgroup (one stress partial each)
+constexpr int kMaxCmdsQ = 8;       // widest subspace of the classical-MDS iteration
 constexpr int kLossRaw = 0;        // raw stress sum (delta - Delta)^2
 constexpr int kLossSammon = 1;     // Sammon stress sum (delta - Delta)^2 / Delta over sum Delta
 
@@ -109,6 +110,19 @@ int64_t rowinv_blocks(int64_t n);
 hipError_t launch_rowinv_max(const float* Delta, int64_t n, int64_t ldd, float* part, float* out, hipStream_t s);
 hipError_t launch_sumsq(const float* Delta, int64_t n, int64_t ldd, int n_mat, int64_t stride, float* part,
                         float* out, int power, hipStream_t s);
+
+// Classical MDS (k_cmds.hip).  out = D^2 V over full rows of Delta (diagonal
+// skipped), V and out n x q row-major, q <= kMaxCmdsQ.
+hipError_t launch_d2v(const float* Delta, int64_t n, int64_t ldd, const float* V, int q, float* out, hipStream_t s);
+// out (qa*qb pairs (hi, lo)) = A^T B over n rows (B == nullptr: column sums of
+// A); `part` holds 2 * qa * qb * gram_blocks(n) floats.
+int64_t gram_blocks(int64_t n);
+hipError_t launch_gram(const float* A, int qa, const float* B, int qb, int64_t n, float* part, float* out,
+                       hipStream_t s);
+// out[i, :] = (alpha (A[i, :] - shift)) M; M qa x qb row-major (device),
+// shift (qa, device) may be null.
+hipError_t launch_rowmat(const float* A, int qa, const float* shift, float alpha, const float* M, int qb, int64_t n,
+                         float* out, int64_t ldo, hipStream_t s);
 
 // Gradient components the stress kernels store per point in the tile
 // partials: the p = 2 Gini gradient is (-g, g), so one; p <= 4 has its own

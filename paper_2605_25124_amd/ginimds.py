@@ -102,11 +102,13 @@ def _load():
                                  P, P, P, P]
     L.gini_alternate_nu.argtypes = [P, P, i64, i32, i64, P, i32, P, i64, ctypes.POINTER(_AlternateOpts), P, i64,
                                     P, P, P, P]
+    L.gini_classical_mds.argtypes = [P, P, i64, i64, i32, i32, f64, P, i64, P, P, P]
     L.gini_profile_enable.argtypes = [P, ctypes.c_int]
     L.gini_profile_read.argtypes = [P, ctypes.POINTER(_Profile)]
     for fn in ("gini_create", "gini_rank", "gini_dissim", "gini_sumsq", "gini_sum", "gini_sammon_fwd",
                "gini_sammon_bwd", "gini_sammon_step", "gini_stress_fwd", "gini_stress_bwd",
-               "gini_mds_solve", "gini_autotune", "gini_select_nu", "gini_alternate_nu", "gini_profile_enable",
+               "gini_mds_solve", "gini_autotune", "gini_select_nu", "gini_alternate_nu", "gini_classical_mds",
+               "gini_profile_enable",
                "gini_profile_read"):
         getattr(L, fn).restype = ctypes.c_int
     return L
@@ -512,6 +514,26 @@ def gini_alternate_nu(X: torch.Tensor, nus: Sequence[float], Z0: torch.Tensor, i
                                    _ptr(Z_out), ldzo, ctypes.c_void_p(hist.ctypes.data),
                                    ctypes.c_void_p(ks.ctypes.data), ctypes.byref(best), _stream(dev)))
     return int(best.value), hist, ks, Z_out
+
+
+def gini_classical_mds(Delta: torch.Tensor, p: int, max_iters: int = 300, tol: float = 1e-7,
+                       Z: Optional[torch.Tensor] = None):
+    """Classical MDS of Delta: (Z[n, p], eigenvalues[p], iterations used)."""
+    import numpy as np
+    dev = _dev_index(Delta)
+    if Delta.dim() != 2 or Delta.shape[0] != Delta.shape[1]:
+        raise ValueError("Delta must be n x n")
+    ldd = _mat(Delta, "Delta")
+    n = int(Delta.shape[0])
+    if Z is None:
+        Z = torch.empty((n, int(p)), dtype=torch.float32, device=Delta.device)
+    ldz = _mat(Z, "Z")
+    ev = np.zeros(int(p), dtype=np.float64)
+    it = ctypes.c_int32(0)
+    c = context(dev)
+    c.check(_lib.gini_classical_mds(c.handle, _ptr(Delta), n, ldd, int(p), int(max_iters), float(tol), _ptr(Z), ldz,
+                                    ctypes.c_void_p(ev.ctypes.data), ctypes.byref(it), _stream(dev)))
+    return Z, ev, int(it.value)
 
 
 def gini_profile_enable(device: int = 0, enable: bool = True) -> None:

@@ -232,6 +232,21 @@ def test_alternate_validation(gm):
     L.gini_destroy(h)
 
 
+def test_classical_mds_validation(gm):
+    L, h = gm._lib, _ctx(gm)
+    D, Z = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    assert L.gini_classical_mds(h, D, 1, 1, 1, 10, 1e-7, Z, 1, None, None, None) == EINVAL
+    assert L.gini_classical_mds(h, D, 10, 9, 2, 10, 1e-7, Z, 2, None, None, None) == EINVAL
+    assert L.gini_classical_mds(h, D, 10, 10, 0, 10, 1e-7, Z, 2, None, None, None) == EINVAL
+    assert L.gini_classical_mds(h, D, 10, 10, 9, 10, 1e-7, Z, 9, None, None, None) == EINVAL   # p > 8
+    assert L.gini_classical_mds(h, D, 3, 3, 3, 10, 1e-7, Z, 3, None, None, None) == EINVAL     # p > n - 1
+    assert L.gini_classical_mds(h, D, 10, 10, 2, 0, 1e-7, Z, 2, None, None, None) == EINVAL
+    assert L.gini_classical_mds(h, D, 10, 10, 2, 10, -1.0, Z, 2, None, None, None) == EINVAL
+    assert L.gini_classical_mds(h, D, 10, 10, 2, 10, 1e-7, Z, 1, None, None, None) == EINVAL
+    assert L.gini_classical_mds(h, None, 10, 10, 2, 10, 1e-7, Z, 2, None, None, None) == EINVAL
+    L.gini_destroy(h)
+
+
 def test_select_validation(gm):
     L, h = gm._lib, _ctx(gm)
     X, Z0, Zo = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)

@@ -475,3 +475,21 @@ def test_alternation_scale_invariance(orc):
     np.testing.assert_allclose(k2, k1, rtol=1e-9)
     np.testing.assert_allclose(Z2, 3.0 * Z1, rtol=1e-9, atol=1e-12)
     assert h1[0] == 1 and all(h1[t + 1] == int(np.argmin(k1[t])) for t in range(2))
+
+
+# --------------------------------------------------------- classical MDS
+def test_classical_mds_recovers_euclidean_configurations(orc):
+    """Textbook: for Euclidean distances of points in R^p, classical MDS
+    returns a configuration with exactly those distances, and the eigenvalues
+    are the squared singular values of the centred points."""
+    g = np.random.Generator(np.random.PCG64(81))
+    Y = g.standard_normal((60, 3)) * np.array([3.0, 1.5, 0.5])
+    D = squareform(pdist(Y))
+    Z, lam = orc.classical_mds(D, 3)
+    np.testing.assert_allclose(squareform(pdist(Z)), D, atol=1e-9)
+    sv = np.linalg.svd(Y - Y.mean(axis=0), compute_uv=False)
+    np.testing.assert_allclose(lam, sv ** 2, rtol=1e-10)
+    # fewer dimensions: the leading principal axes
+    Z2, lam2 = orc.classical_mds(D, 2)
+    np.testing.assert_allclose(lam2, lam[:2], rtol=1e-12)
+    np.testing.assert_allclose(np.abs(Z2), np.abs(Z[:, :2]), atol=1e-9)
