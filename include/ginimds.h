@@ -369,6 +369,20 @@ gini_status gini_classical_mds(gini_ctx* ctx, const float* Delta, int64_t n, int
                                int32_t max_iters, double tol, float* Z, int64_t ldz, double* eigvals,
                                int32_t* iters_done, gini_stream_t stream);
 
+/*
+ * gini_standardize -- the preprocessing of the simulations of Section V-C:
+ * every column of X is centred to zero median and scaled to unit variance,
+ *     Y[i, c] = (X[i, c] - median_c) / sd_c,
+ * median_c the middle order statistic (the mean of the two middle ones for
+ * even n, found exactly), sd_c the population standard deviation about the
+ * mean (a constant column is only centred).  The dissimilarities depend on
+ * differences of rows only, so only the scaling changes them.  X, Y: n x m
+ * FP32 (ldx, ldy >= m); Y may be X (then ldy == ldx).  stats: device
+ * float[2m], (median, sd) per column, or NULL.  n >= 1, m >= 1.
+ */
+gini_status gini_standardize(gini_ctx* ctx, const float* X, int64_t n, int32_t m, int64_t ldx, float* Y,
+                             int64_t ldy, float* stats, gini_stream_t stream);
+
 /* Kernel timing collected by the context while profiling is enabled: HIP
  * events recorded on the launching stream around each stress-tile launch,
  * each reduction launch and each persistent launch. */

@@ -256,6 +256,14 @@ def classical_mds(Delta, p: int):
     return V[:, order] * np.sqrt(np.maximum(lam, 0.0)), lam
 
 
+def standardize(X):
+    """Section V-C preprocessing: columns to zero median, unit population variance."""
+    X = np.asarray(X, dtype=np.float64)
+    sd = X.std(axis=0)
+    sd = np.where(sd > 0, sd, 1.0)
+    return (X - np.median(X, axis=0)) / sd
+
+
 def grad_rows(Drows, rows, Z, nu: float, latent: int = LATENT_GINI, mode: int = MATCH32):
     """Gradient rows G[rows] from the corresponding rows of Delta; also returns
     the partial sum over the selected rows of sum_{j>i} r_ij^2."""

@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libginimds.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["k_stress.hip", "k_stress_sammon.hip", "k_dissim.hip", "k_rank.hip", "k_sumsq.hip", "k_cmds.hip", "api.cpp"]
+SOURCES = ["k_stress.hip", "k_stress_sammon.hip", "k_dissim.hip", "k_rank.hip", "k_sumsq.hip", "k_cmds.hip", "k_prep.hip", "api.cpp"]
 ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -1517,4 +1517,21 @@ gini_status gini_classical_mds(gini_ctx* c, const float* Delta, int64_t n, int64
     return GINI_OK;
 }
 
+gini_status gini_standardize(gini_ctx* c, const float* X, int64_t n, int32_t m, int64_t ldx, float* Y, int64_t ldy,
+                             float* stats, gini_stream_t stream) {
+    if (!c) return GINI_EINVAL;
+    c->err.clear();
+    if (!X || !Y) return fail(c, GINI_EINVAL, "X and Y must be non-null");
+    if (n < 1) return fail(c, GINI_EINVAL, "n = %lld < 1", (long long)n);
+    if (m < 1) return fail(c, GINI_EINVAL, "m = %d < 1", m);
+    if (ldx < m || ldy < m) return fail(c, GINI_EINVAL, "ldx and ldy must be >= m = %d", m);
+    if (X == Y && ldx != ldy) return fail(c, GINI_EINVAL, "in place needs ldy == ldx");
+    if (n > ((int64_t)1 << 32) - 1) return fail(c, GINI_EUNSUPPORTED, "n too large");
+    if (m > 65535) return fail(c, GINI_EUNSUPPORTED, "m > 65535 is not supported");
+    gini_status st = ensure_ready(c);
+    if (st != GINI_OK) return st;
+    GINI_HIP(c, gmds::launch_standardise(X, n, m, ldx, Y, ldy, stats, reinterpret_cast<hipStream_t>(stream)));
+    return GINI_OK;
+}
+
 }  // extern "C"

@@ -124,6 +124,12 @@ hipError_t launch_gram(const float* A, int qa, const float* B, int qb, int64_t n
 hipError_t launch_rowmat(const float* A, int qa, const float* shift, float alpha, const float* M, int qb, int64_t n,
                          float* out, int64_t ldo, hipStream_t s);
 
+// Column standardisation (k_prep.hip): Y = (X - median) / sd per column
+// (population sd; a constant column is only centred); stats (2m floats,
+// (median, sd) per column) may be null.  Y may alias X only if ldy == ldx.
+hipError_t launch_standardise(const float* X, int64_t n, int m, int64_t ldx, float* Y, int64_t ldy, float* stats,
+                              hipStream_t s);
+
 // Gradient components the stress kernels store per point in the tile
 // partials: the p = 2 Gini gradient is (-g, g), so one; p <= 4 has its own
 // kernel; larger p runs the kMaxP kernel, which stores kMaxP.

@@ -103,12 +103,13 @@ def _load():
     L.gini_alternate_nu.argtypes = [P, P, i64, i32, i64, P, i32, P, i64, ctypes.POINTER(_AlternateOpts), P, i64,
                                     P, P, P, P]
     L.gini_classical_mds.argtypes = [P, P, i64, i64, i32, i32, f64, P, i64, P, P, P]
+    L.gini_standardize.argtypes = [P, P, i64, i32, i64, P, i64, P, P]
     L.gini_profile_enable.argtypes = [P, ctypes.c_int]
     L.gini_profile_read.argtypes = [P, ctypes.POINTER(_Profile)]
     for fn in ("gini_create", "gini_rank", "gini_dissim", "gini_sumsq", "gini_sum", "gini_sammon_fwd",
                "gini_sammon_bwd", "gini_sammon_step", "gini_stress_fwd", "gini_stress_bwd",
                "gini_mds_solve", "gini_autotune", "gini_select_nu", "gini_alternate_nu", "gini_classical_mds",
-               "gini_profile_enable",
+               "gini_standardize", "gini_profile_enable",
                "gini_profile_read"):
         getattr(L, fn).restype = ctypes.c_int
     return L
@@ -534,6 +535,21 @@ def gini_classical_mds(Delta: torch.Tensor, p: int, max_iters: int = 300, tol: f
     c.check(_lib.gini_classical_mds(c.handle, _ptr(Delta), n, ldd, int(p), int(max_iters), float(tol), _ptr(Z), ldz,
                                     ctypes.c_void_p(ev.ctypes.data), ctypes.byref(it), _stream(dev)))
     return Z, ev, int(it.value)
+
+
+def gini_standardize(X: torch.Tensor, out: Optional[torch.Tensor] = None, stats: bool = False):
+    """Columns centred to zero median and scaled to unit (population) variance.
+    Returns Y, or (Y, (m, 2) tensor of (median, sd)) with stats=True."""
+    dev = _dev_index(X)
+    ldx = _mat(X, "X")
+    n, m = X.shape
+    if out is None:
+        out = torch.empty((n, m), dtype=torch.float32, device=X.device)
+    ldy = _mat(out, "out")
+    st = torch.empty((m, 2), dtype=torch.float32, device=X.device) if stats else None
+    c = context(dev)
+    c.check(_lib.gini_standardize(c.handle, _ptr(X), n, m, ldx, _ptr(out), ldy, _ptr(st), _stream(dev)))
+    return (out, st) if stats else out
 
 
 def gini_profile_enable(device: int = 0, enable: bool = True) -> None:

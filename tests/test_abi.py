@@ -247,6 +247,18 @@ def test_classical_mds_validation(gm):
     L.gini_destroy(h)
 
 
+def test_standardize_validation(gm):
+    L, h = gm._lib, _ctx(gm)
+    X, Y = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    assert L.gini_standardize(h, X, 0, 3, 3, Y, 3, None, None) == EINVAL
+    assert L.gini_standardize(h, X, 10, 0, 3, Y, 3, None, None) == EINVAL
+    assert L.gini_standardize(h, X, 10, 4, 3, Y, 4, None, None) == EINVAL
+    assert L.gini_standardize(h, X, 10, 4, 4, Y, 3, None, None) == EINVAL
+    assert L.gini_standardize(h, X, 10, 4, 4, X, 5, None, None) == EINVAL and "in place" in _err(gm, h)
+    assert L.gini_standardize(h, None, 10, 4, 4, Y, 4, None, None) == EINVAL
+    L.gini_destroy(h)
+
+
 def test_select_validation(gm):
     L, h = gm._lib, _ctx(gm)
     X, Z0, Zo = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)

@@ -493,3 +493,19 @@ def test_classical_mds_recovers_euclidean_configurations(orc):
     Z2, lam2 = orc.classical_mds(D, 2)
     np.testing.assert_allclose(lam2, lam[:2], rtol=1e-12)
     np.testing.assert_allclose(np.abs(Z2), np.abs(Z[:, :2]), atol=1e-9)
+
+
+def test_standardize_properties(orc):
+    """Zero median, unit population variance, invariance under a positive
+    affine map of each column, and Gini dissimilarities that change only by
+    the per-column scale (differences remove the centre)."""
+    g = np.random.Generator(np.random.PCG64(91))
+    X = g.standard_t(3, size=(51, 6))
+    Y = orc.standardize(X)
+    np.testing.assert_allclose(np.median(Y, axis=0), 0.0, atol=1e-15)
+    np.testing.assert_allclose(Y.var(axis=0), 1.0, rtol=1e-12)
+    a, b = g.uniform(0.5, 3.0, 6), g.uniform(-5, 5, 6)
+    np.testing.assert_allclose(orc.standardize(a * X + b), Y, rtol=1e-10, atol=1e-12)
+    Xs = X / X.std(axis=0)
+    np.testing.assert_allclose(orc.dissim(Y, [2.0], orc.EXACT), orc.dissim(Xs, [2.0], orc.EXACT), rtol=1e-12,
+                               atol=1e-12)
