@@ -234,42 +234,50 @@ __global__ __launch_bounds__(kDWG) void k_dissim_lane(DissimArgs A, int nu0, int
 
 // ---------------------------------------------------- G lanes per pair
 // Element e = g*E + r of the virtual array lives in register r of group lane g.
+// Every compare-exchange whose direction is only known at run time (per lane)
+// is one median-of-three per output: med3(a, b, -inf) = min(a, b) and
+// med3(a, b, +inf) = max(a, b), so a lane keeps the minimum or the maximum by
+// the sign of one constant instead of computing both and selecting.
+__device__ __forceinline__ float med3(float a, float b, float c) { return __builtin_amdgcn_fmed3f(a, b, c); }
+
 template <int G, int E>
 __device__ __forceinline__ void bitonic_blocked(float (&v)[E], int g) {
     constexpr int N = G * E;
+    const float inf = __builtin_inff();
     static_for<ilog2(N)>([&](auto kc) {
         constexpr int k = 2 << decltype(kc)::value;
-        // Blocks of size k with (e & k) != 0 are sorted descending; for
-        // k >= E that is a per-lane property, handled by negating the lane's
-        // values for the duration of the stage and sorting ascending.
+        // blocks of size k with (e & k) != 0 are sorted descending; for
+        // k >= E that is the same for every register of a lane
         const bool lane_desc = (k >= E) && (k < N) && (((g * E) & k) != 0);
-        if (lane_desc) {
-            static_for<E>([&](auto rc) { v[decltype(rc)::value] = -v[decltype(rc)::value]; });
-        }
+        const float ld = lane_desc ? inf : -inf;          // first of a pair keeps max if descending
         static_for<ilog2(k)>([&](auto sc) {
             constexpr int st = (k >> 1) >> decltype(sc)::value;
             if constexpr (st >= E) {
                 const int ls = st / E;
                 const bool lower = (g & ls) == 0;
+                const float keep = (lower != lane_desc) ? -inf : inf;   // -inf keeps the minimum
                 static_for<E>([&](auto rc) {
                     constexpr int r = decltype(rc)::value;
                     const float o = __shfl_xor(v[r], ls, G);
-                    v[r] = lower ? fminf(v[r], o) : fmaxf(v[r], o);
+                    v[r] = med3(v[r], o, keep);
                 });
             } else {
                 static_for<E>([&](auto rc) {
                     constexpr int r = decltype(rc)::value;
                     if constexpr ((r & st) == 0) {
-                        constexpr bool desc = (k < E) && ((r & k) != 0);
-                        if constexpr (desc) cex(v[r | st], v[r]);
-                        else cex(v[r], v[r | st]);
+                        if constexpr (k < E) {
+                            constexpr bool desc = (r & k) != 0;
+                            if constexpr (desc) cex(v[r | st], v[r]);
+                            else cex(v[r], v[r | st]);
+                        } else {
+                            const float a = v[r], b = v[r | st];
+                            v[r] = med3(a, b, ld);
+                            v[r | st] = med3(a, b, -ld);
+                        }
                     }
                 });
             }
         });
-        if (lane_desc) {
-            static_for<E>([&](auto rc) { v[decltype(rc)::value] = -v[decltype(rc)::value]; });
-        }
     });
 }
 
@@ -438,7 +446,7 @@ hipError_t launch_dissim(const DissimArgs& a, hipStream_t s) {
     if (a.n == 1) {
         // a single row: only the zero diagonal
         for (int q = 0; q < a.n_nu; ++q) {
-            hipError_t e = hipMemsetAsync(a.Delta + (int64_t)q * a.stride_nu, 0, sizeof(float), s);
+            hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(a.Delta + (int64_t)q * a.stride_nu), 1, 0u, s);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;
