@@ -377,13 +377,17 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
             }
         }
     }
-    // stress: one compensated partial per wave (fixed butterfly, lane 0's copy)
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        Comp other;
-        other.hi = __shfl_xor(sig.hi, o, 64);
-        other.lo = __shfl_xor(sig.lo, o, 64);
-        sig.add(other);
+    // stress: one partial per wave.  Each lane's compensated pair (hi, lo) is
+    // summed over the wave part by part, in a fixed tree: rotation sums within
+    // each row of 16 lanes, then the four rows.
+    {
+        float h = row16_sum(sig.hi), l = row16_sum(sig.lo);
+        h += __shfl_xor(h, 16, 64);
+        l += __shfl_xor(l, 16, 64);
+        h += __shfl_xor(h, 32, 64);
+        l += __shfl_xor(l, 32, 64);
+        sig.hi = h;
+        sig.lo = l;
     }
     if ((tid & 63) == 0) {
         const int64_t slot = (lt * UNITS + sub) * kWaves + (tid >> 6);
