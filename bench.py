@@ -60,7 +60,7 @@ def parse():
 
 PROFILE = os.path.join(ROOT, "profiles", "k_stress_units_images_n10000.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2605_25124_amd", "csrc", f)
-                  for f in ("k_stress.hip", "common.hpp", "kernels.hpp")]
+                  for f in ("k_stress.hip", "stress_impl.hpp", "common.hpp", "kernels.hpp")]
 
 
 def measured_traffic(kernel, n, tile):

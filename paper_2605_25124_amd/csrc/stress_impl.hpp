@@ -79,8 +79,9 @@ __device__ __forceinline__ float row16_sum(float x) {
     return x;
 }
 
-// Stress term of one pair and its gradient term g (without the common factor),
-// both weighted by the loss's pair weight w: w r^2 and w r d delta / d Z_i.
+// Stress term of one pair, added to sst with one FMA, and its gradient term g
+// (without the common factor), both weighted by the loss's pair weight w:
+// w r^2 and w r d delta / d Z_i.
 // MASK: `valid` zeroes pairs outside the strict upper triangle or past n.
 // u_c = fl32(Z_i,c - Z_j,c).  Gini: doubled midranks t_c of u over its p
 // coordinates, a_c = (p/2) W_p[t_c], delta = sum_c u_c a_c, g = r a.
@@ -94,8 +95,8 @@ __device__ __forceinline__ float weigh(float r, float d) {
 }
 
 template <int P, int LAT, int LOSS, bool GRAD, bool MASK>
-__device__ __forceinline__ float pair_term(const float (&zi)[P], const float (&zj)[P], float d, bool valid,
-                                           int p, const InstDesc& D, float (&g)[PG_<P, LAT>::value]) {
+__device__ __forceinline__ void pair_term(const float (&zi)[P], const float (&zj)[P], float d, bool valid,
+                                          int p, const InstDesc& D, float (&g)[PG_<P, LAT>::value], float& sst) {
     constexpr int PG = PG_<P, LAT>::value;
     float u[P];
 #pragma unroll
@@ -109,7 +110,7 @@ __device__ __forceinline__ float pair_term(const float (&zi)[P], const float (&z
         if constexpr (MASK) r = valid ? r : 0.f;
         const float rw = weigh<LOSS>(r, d);
         if constexpr (GRAD) g[0] = (w > 0.f) ? rw : ((w < 0.f) ? -rw : 0.f);
-        return r * rw;
+        sst = fmaf(r, rw, sst);
     } else if constexpr (P == 3 && LAT == 0) {
         // Untied u takes the doubled midranks (2, 4, 6) in sorted order, and the
         // middle weight is exactly 0, so delta = a_max u_max + a_min u_min with
@@ -144,7 +145,7 @@ __device__ __forceinline__ float pair_term(const float (&zi)[P], const float (&z
 #pragma unroll
             for (int c = 0; c < 3; ++c) g[c] = rw * a[c];
         }
-        return r * rw;
+        sst = fmaf(r, rw, sst);
     } else if constexpr (LAT == 0) {
         float a[P];
         float delta = 0.f;
@@ -168,7 +169,7 @@ __device__ __forceinline__ float pair_term(const float (&zi)[P], const float (&z
 #pragma unroll
             for (int c = 0; c < PG; ++c) g[c] = rw * a[c];
         }
-        return r * rw;
+        sst = fmaf(r, rw, sst);
     } else {
         float ss = 0.f;
 #pragma unroll
@@ -182,7 +183,7 @@ __device__ __forceinline__ float pair_term(const float (&zi)[P], const float (&z
 #pragma unroll
             for (int c = 0; c < PG; ++c) g[c] = f * u[c];
         }
-        return r * rw;
+        sst = fmaf(r, rw, sst);
     }
 }
 
@@ -326,23 +327,59 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
 #pragma unroll
         for (int c = 0; c < PG; ++c) rowacc[c] = 0.f;
         float sst = 0.f;
+        // p = 2 Gini on an interior tile: unless some pair of the step is tied
+        // (w = u2 - u1 = 0) somewhere in the wave, the gradient term is the
+        // weighted residual with the sign of w flipped in (sign-bit xor),
+        // which equals the general rule's select bit for bit.
+        bool fast = false;
+        float w2[CPT];
+        if constexpr (P == 2 && LAT == 0 && !MASK) {
+            bool tie = false;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q)
+            for (int x = 0; x < CPT; ++x) {
+                w2[x] = (zi[1] - zj[x][1]) - (zi[0] - zj[x][0]);
+                tie |= (w2[x] == 0.f);
+            }
+            fast = __builtin_amdgcn_ballot_w64(tie) == 0;
+        }
+        if (fast) {
+            if constexpr (P == 2 && LAT == 0 && !MASK) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int x = q * 4 + e;
-                const int64_t j = j0 + 4 * (c4 + q * kLPR) + e;
-                const bool valid = !MASK || ((j > i) && (j < n) && (i < n));
-                float g[PG];
-                sst += pair_term<P, LAT, LOSS, GRAD, MASK>(zi, zj[x], buf[q][e], valid, p, D, g);
-                if constexpr (GRAD) {
+                for (int q = 0; q < NQ; ++q)
 #pragma unroll
-                    for (int c = 0; c < PG; ++c) {
-                        rowacc[c] += g[c];
-                        colacc[x][c] += g[c];
+                    for (int e = 0; e < 4; ++e) {
+                        const int x = q * 4 + e;
+                        const float d = buf[q][e];
+                        const float r = fmaf(D.c2, fabsf(w2[x]), -d);
+                        const float rw = weigh<LOSS>(r, d);
+                        sst = fmaf(r, rw, sst);
+                        if constexpr (GRAD) {
+                            const float g = __int_as_float(__float_as_int(rw) ^
+                                                           (__float_as_int(w2[x]) & (int)0x80000000u));
+                            rowacc[0] += g;
+                            colacc[x][0] += g;
+                        }
+                    }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int x = q * 4 + e;
+                    const int64_t j = j0 + 4 * (c4 + q * kLPR) + e;
+                    const bool valid = !MASK || ((j > i) && (j < n) && (i < n));
+                    float g[PG];
+                    pair_term<P, LAT, LOSS, GRAD, MASK>(zi, zj[x], buf[q][e], valid, p, D, g, sst);
+                    if constexpr (GRAD) {
+#pragma unroll
+                        for (int c = 0; c < PG; ++c) {
+                            rowacc[c] += g[c];
+                            colacc[x][c] += g[c];
+                        }
                     }
                 }
-            }
+        }
         if constexpr (GRAD) {
 #pragma unroll
             for (int c = 0; c < PG; ++c) {
