@@ -25,6 +25,11 @@ def _problem(gm, n, m, p, seed, nu=2.0, scale=0.5, ties=False):
         Z[3] = Z[4]
         Z[5, 0] = Z[5, 1]
         Z[6, :] = 0.25
+    if ties and n > 140:
+        # tied pairs in off-diagonal tiles as well: a coincident point and a
+        # second point with equal coordinates (u_1 = u_2 against row 6)
+        Z[n // 2 + 1] = Z[3]
+        Z[n // 2, :] = 0.75
     D = gm.gini_dissim(torch.from_numpy(X).to(DEV), [nu])[0]
     return D, torch.from_numpy(Z).to(DEV)
 
@@ -59,9 +64,10 @@ def test_stress_parity_dims(gm, orc, latent, p, nu):
     _compare(gm, orc, D, Z, nu, latent, f"p={p} nu={nu} latent={latent}")
 
 
+@pytest.mark.parametrize("n", [150, 1000])
 @pytest.mark.parametrize("latent,p,nu", [(0, 2, 2.0), (0, 3, 1.5), (0, 4, 3.0), (1, 2, 2.0)])
-def test_stress_latent_ties(gm, orc, latent, p, nu):
-    D, Z = _problem(gm, 150, 5, p, 5, nu=nu, ties=True)
+def test_stress_latent_ties(gm, orc, n, latent, p, nu):
+    D, Z = _problem(gm, n, 5, p, 5, nu=nu, ties=True)
     _compare(gm, orc, D, Z, nu, latent, "ties")
 
 
