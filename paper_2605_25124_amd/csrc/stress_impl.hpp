@@ -21,9 +21,10 @@
 // Reduction.  A unit writes one partial per row (complete for that tile), one
 // partial per column and its stress.  A second launch sums, for every point, the
 // row partials of its tile row and the column partials of its tile column in a
-// fixed order (sixteen interleaved Neumaier sums, one wave each over 64
-// consecutive points, combined in index order), and either writes the
-// gradient or takes the descent step.  No floating-point
+// fixed order (S interleaved Neumaier sums, S a power of two up to 16 fixed by
+// the instance's tile count, one wave each over 64 consecutive points,
+// combined in index order), and either writes the gradient or takes the
+// descent step.  No floating-point
 // atomics anywhere: results are bitwise reproducible and independent of
 // scheduling and of how many instances share a launch.
 #pragma once
@@ -38,8 +39,8 @@ namespace gmds {
 constexpr int kWG = 256;
 constexpr int kLPR = 16;                 // lanes per tile row = one DPP row
 constexpr int kRPS = kWG / kLPR;         // rows per step
-constexpr int kSplit = 16;               // interleaved partial sums per point in the reduction
-constexpr int kBatch = 8;                // loads in flight per partial sum
+constexpr int kSplit = 16;               // interleaved partial sums per point in the reduction (at most)
+constexpr int kBatch = 8;                // loads in flight per stress-slice sum
 constexpr int kWaves = kStressWaves;     // waves per workgroup (one stress partial each)
 static_assert(kWaves * 64 == kWG, "one stress partial per wave");
 
@@ -461,95 +462,118 @@ __device__ __forceinline__ float loss_factor(const InstDesc& D) {
     return 2.f;
 }
 
-// Partial gradient of point k: terms t = s, s + kSplit, ... of the sequence
+// Loads in flight per partial gradient sum: 16 floats of registers.
+__host__ __device__ constexpr int red_batch(int pg) { return pg >= 8 ? 2 : 16 / pg; }
+
+// Interleaved partial sums per point, S: the fewest (a power of two, at most
+// kSplit) for which every sum takes one batch of loads.  The longest sequence
+// of terms is that of the last tile row, 1 + nb * units.  A reduction group
+// covers kSplit / S runs of kNPT points (kSplit * kNPT partial sums).
+__host__ __device__ inline int red_split(int64_t nb, int units, int pg) {
+    const int64_t need = (1 + nb * units + red_batch(pg) - 1) / red_batch(pg);
+    int sp = 1;
+    while (sp < kSplit && sp < need) sp <<= 1;
+    return sp;
+}
+__host__ __device__ inline int red_points(int64_t nb, int units, int pg) {
+    return kSplit / red_split(nb, units, pg) * kNPT;
+}
+
+// Partial gradient of point k: terms t = s, s + S, ... of the sequence
 // "row partials of its tile row (tiles (b, b..nb-1)), then column partials of
 // its tile column (every unit of tiles (0..b, b))", summed (Neumaier) in
 // increasing t.  The loads of a batch are in flight together; an absent term
 // adds an exact 0.
 template <int P, int LAT, int T>
-__device__ __forceinline__ void point_partial(const InstDesc& D, int64_t k, int s, Comp (&acc)[PG_<P, LAT>::value]) {
+__device__ __forceinline__ void point_partial(const InstDesc& D, int64_t k, int s, int S,
+                                              Comp (&acc)[PG_<P, LAT>::value]) {
     constexpr int PG = PG_<P, LAT>::value;
     constexpr int UNITS = TileShape<T>::UNITS;
-    const int64_t b = k / T;
+    constexpr int RB = red_batch(PG);
+    // Tile and unit indices fit 32 bits: the host caps an instance's work
+    // units at 2^31 - 1, so nb^2 < 2^32; element offsets are taken in 64 bits.
+    const uint32_t b = (uint32_t)(k / T);
     const int64_t kl = k % T;
-    const int64_t nb = D.nb;
-    const int64_t nrow = nb - b;
-    const int64_t nterm = nrow + (b + 1) * UNITS;
-    const int64_t last_lt = tri_count(nb) - 1;
-    gfl* rp = gp(D.rowpart);
-    gfl* cp = gp(D.colpart);
-    for (int64_t t0 = s; t0 < nterm; t0 += (int64_t)kSplit * kBatch) {
-        float v[kBatch][PG];
+    const uint32_t nb = (uint32_t)D.nb;
+    const int nrow = (int)(nb - b);
+    const int nterm = nrow + (int)(b + 1) * UNITS;
+    gfl* rbase = gp(D.rowpart) + (tri_index(b, b, nb) * T + kl) * PG;   // row tiles (b, b..) are consecutive
+    gfl* cbase = gp(D.colpart) + kl * PG;
+    for (int t0 = s; t0 < nterm; t0 += S * RB) {
+        float v[RB][PG];
 #pragma unroll
-        for (int q = 0; q < kBatch; ++q) {
-            const int64_t t = t0 + (int64_t)q * kSplit;
+        for (int q = 0; q < RB; ++q) {
+            const int t = t0 + q * S;
             if (t < nrow) {
-                const int64_t lt = tri_index(b, b + t, nb);
 #pragma unroll
-                for (int c = 0; c < PG; ++c) v[q][c] = rp[(lt * T + kl) * PG + c];
+                for (int c = 0; c < PG; ++c) v[q][c] = rbase[t * (T * PG) + c];
             } else {
-                const int64_t tc = t - nrow;
-                const int64_t I = tc / UNITS;
-                const int u = (int)(tc % UNITS);
-                const int64_t lt = tri_index(I, b, nb);
+                const uint32_t tc = (uint32_t)(t - nrow);
+                const uint32_t I = tc / UNITS;
+                const uint32_t u = tc % UNITS;
+                const uint32_t lt = I * nb - (I * (I - 1)) / 2 + (b - I);
                 // units past n (only in the last tile) were never written
-                const bool ok = (t < nterm) && !(lt == last_lt && I * T + (int64_t)u * TileShape<T>::UR >= D.n);
+                const bool ok = (t < nterm) && !(I == nb - 1 && (int64_t)I * T + (int64_t)u * TileShape<T>::UR >= D.n);
+                const uint64_t off = (uint64_t)(lt * UNITS + u) * (T * PG);
 #pragma unroll
-                for (int c = 0; c < PG; ++c) v[q][c] = ok ? -cp[((lt * UNITS + u) * T + kl) * PG + c] : 0.f;
+                for (int c = 0; c < PG; ++c) v[q][c] = ok ? -cbase[off + c] : 0.f;
             }
         }
 #pragma unroll
-        for (int q = 0; q < kBatch; ++q)
+        for (int q = 0; q < RB; ++q)
 #pragma unroll
             for (int c = 0; c < PG; ++c) acc[c].add(v[q][c]);
     }
 }
 
-// Gradient of the kNPT points k0 .. k0+kNPT-1: the kSplit partial sums of each
-// point (one wave per partial sum: 64 consecutive points, coalesced loads)
-// are added in index order, scaled by the common factor and applied.  NT is
-// the number of threads executing the call.  LDS: 2 * kSplit * kNPT * PG floats.
+// Gradient of the points k0 .. k0 + red_points - 1 (a reduction group): the
+// S partial sums of each point (one wave per partial sum of 64 consecutive
+// points, coalesced loads) are added in index order, scaled by the common
+// factor and applied.  NT is the number of threads executing the call.  LDS:
+// 2 * kSplit * kNPT * PG floats.
 template <int P, int LAT, int T, int NT>
 __device__ void reduce_group(const InstDesc& D, int64_t k0, int mode, float* lds) {
     constexpr int PG = PG_<P, LAT>::value;
+    constexpr int UNITS = TileShape<T>::UNITS;
     const int tid = threadIdx.x;
     const int p = (P == kMaxP) ? D.p : P;
+    const int S = red_split(D.nb, UNITS, PG);
+    const int np = kSplit / S * kNPT;
     // the combining threads fetch what they update before the partial sums
     // arrive, so that its latency overlaps theirs
-    const bool comb = tid < kNPT && k0 + tid < D.n;
+    const bool comb = tid < np && k0 + tid < D.n;
     float zold[P];
     float sc = 1.f;
-    if (comb) {
-        if (mode == kModeGrad) {
-            if (D.grad_out) sc = *D.grad_out;
-        } else {
+    if (mode == kModeGrad) {
+        if (D.grad_out) sc = *D.grad_out;
+    } else if (comb) {
 #pragma unroll
-            for (int c = 0; c < P; ++c) zold[c] = (c < p) ? D.Z[(k0 + tid) * D.ldz + c] : 0.f;
-        }
+        for (int c = 0; c < P; ++c) zold[c] = (c < p) ? D.Z[(k0 + tid) * D.ldz + c] : 0.f;
     }
     for (int item = tid; item < kSplit * kNPT; item += NT) {
-        const int sp = item / kNPT;
+        const int slot = item / kNPT;            // run (slot / S), partial sum (slot % S)
         const int pl = item % kNPT;
-        const int64_t k = k0 + pl;
+        const int64_t k = k0 + (int64_t)(slot / S) * kNPT + pl;
         Comp acc[PG];
-        if (k < D.n) point_partial<P, LAT, T>(D, k, sp, acc);
+        if (k < D.n) point_partial<P, LAT, T>(D, k, slot % S, S, acc);
 #pragma unroll
         for (int c = 0; c < PG; ++c) {
-            lds[((c * kSplit + sp) * kNPT + pl) * 2] = acc[c].hi;
-            lds[((c * kSplit + sp) * kNPT + pl) * 2 + 1] = acc[c].lo;
+            lds[((c * kSplit + slot) * kNPT + pl) * 2] = acc[c].hi;
+            lds[((c * kSplit + slot) * kNPT + pl) * 2 + 1] = acc[c].lo;
         }
     }
     __syncthreads();
-    if (comb) {
-        const int pl = tid;
-        const int64_t k = k0 + pl;
+    for (int pt = tid; pt < np; pt += NT) {
+        const int64_t k = k0 + pt;
+        if (k >= D.n) break;
+        const int g = pt / kNPT, pl = pt % kNPT;
         Comp tot[PG];
 #pragma unroll
         for (int c = 0; c < PG; ++c)
-            for (int q = 0; q < kSplit; ++q) {
+            for (int q = 0; q < S; ++q) {
                 Comp x;
-                x.hi = lds[((c * kSplit + q) * kNPT + pl) * 2];
-                x.lo = lds[((c * kSplit + q) * kNPT + pl) * 2 + 1];
+                x.hi = lds[((c * kSplit + g * S + q) * kNPT + pl) * 2];
+                x.lo = lds[((c * kSplit + g * S + q) * kNPT + pl) * 2 + 1];
                 tot[c].add(x);
             }
         float G[P];
@@ -566,6 +590,10 @@ __device__ void reduce_group(const InstDesc& D, int64_t k0, int mode, float* lds
             for (int c = 0; c < P; ++c)
                 if (c < p) D.gradZ[k * D.ldg + c] = sc * G[c];
         } else {
+            if (pt != tid) {
+#pragma unroll
+                for (int c = 0; c < P; ++c) zold[c] = (c < p) ? D.Z[k * D.ldz + c] : 0.f;
+            }
 #pragma unroll
             for (int c = 0; c < P; ++c)
                 if (c < p) D.Z[k * D.ldz + c] = zold[c] - D.eta * G[c];
@@ -700,13 +728,6 @@ __global__ __launch_bounds__(kWG) void k_stress_units(const InstDesc* __restrict
     stress_unit<P, LAT, LOSS, T, GRAD>(D, q - D.tile_off, lds);
 }
 
-// Number of reduction blocks of an instance: its stress slices, then one
-// block per kNPT points.
-template <int T>
-__device__ __forceinline__ int64_t reduce_blocks(const InstDesc& D) {
-    return sigma_slices<T>(D) + (D.n + kNPT - 1) / kNPT;
-}
-
 template <int PG>
 constexpr int reduce_lds_floats() {
     return 2 * kSplit * kNPT * PG > 2 * kVT ? 2 * kSplit * kNPT * PG : 2 * kVT;
@@ -715,7 +736,7 @@ constexpr int reduce_lds_floats() {
 // Reduction launch over the concatenated blocks of all instances (block
 // offsets in red_off).  The first blocks of an instance sum one slice of its
 // stress each (with several slices, the last to finish adds them in order);
-// the following blocks take kNPT points each.
+// the following blocks take one reduction group (red_points points) each.
 template <int P, int LAT, int T>
 __global__ __launch_bounds__(kRedWG) void k_stress_reduce(const InstDesc* __restrict__ dd, int n_inst,
                                                           int64_t q_base, int mode, int it) {
@@ -761,7 +782,7 @@ __global__ __launch_bounds__(kRedWG) void k_stress_reduce(const InstDesc* __rest
         return;
     }
     if (mode == kModeSigma) return;
-    reduce_group<P, LAT, T, kRedWG>(D, (b - ns) * kNPT, mode, lds);
+    reduce_group<P, LAT, T, kRedWG>(D, (b - ns) * red_points(D.nb, TileShape<T>::UNITS, PG), mode, lds);
 }
 
 // Persistent solver.  Queue item q = (iteration it, instance k, local unit),
@@ -849,7 +870,8 @@ __global__ __launch_bounds__(kWG) void k_solve_persistent(const InstDesc* __rest
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             const Comp s = instance_sigma<T, kWG>(D, lds);
             write_sigma(D, kModeDescent, it, s);
-            for (int64_t k0 = 0; k0 < D.n; k0 += kNPT) reduce_group<P, LAT, T, kWG>(D, k0, kModeDescent, lds);
+            const int64_t np = red_points(D.nb, UNITS, PG);
+            for (int64_t k0 = 0; k0 < D.n; k0 += np) reduce_group<P, LAT, T, kWG>(D, k0, kModeDescent, lds);
             __threadfence();
             __syncthreads();
             if (tid == 0) {
