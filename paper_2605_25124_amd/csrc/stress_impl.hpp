@@ -114,7 +114,7 @@ __device__ __forceinline__ void pair_term(const float (&zi)[P], const float (&zj
         sst = fmaf(r, rw, sst);
     } else if constexpr (P == 3 && LAT == 0) {
         // Untied u takes the doubled midranks (2, 4, 6) in sorted order, and the
-        // middle weight is exactly 0, so delta = a_max u_max + a_min u_min with
+        // middle weight is exactly 0, so delta = a_max (u_max - u_min) with
         // a_max = (3/2) W_3[6] = -a_min.  A tie (rare) takes the general rule.
         const float mx = fmaxf(fmaxf(u[0], u[1]), u[2]);
         const float mn = fminf(fminf(u[0], u[1]), u[2]);
@@ -122,7 +122,7 @@ __device__ __forceinline__ void pair_term(const float (&zi)[P], const float (&zj
         float r, a[3];
         if (!tie) {
             const float wmax = D.wtab[4], wmin = D.wtab[0];
-            r = fmaf(wmax, mx, wmin * mn) - d;
+            r = fmaf(wmax, mx - mn, -d);
 #pragma unroll
             for (int c = 0; c < 3; ++c) a[c] = (u[c] == mx) ? wmax : ((u[c] == mn) ? wmin : 0.f);
         } else {
@@ -362,6 +362,54 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
                         }
                     }
             }
+        } else if constexpr (P == 3 && LAT == 0 && !MASK) {
+            // p = 3 Gini on an interior tile.  An untied pair's gradient term is
+            // +h on its largest coordinate, -h on its smallest and 0 on the
+            // middle one (h = weighted residual times a_max), so it sums to
+            // zero over the coordinates: only components 0 and 1 are
+            // accumulated, and component 2 collects the coordinate sums of the
+            // tied pairs (general rule), from which it is recovered per row
+            // and per column as sum - c0 - c1.
+            const float wmax = D.wtab[4];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int x = q * 4 + e;
+                    const float d = buf[q][e];
+                    const float u0 = zi[0] - zj[x][0], u1 = zi[1] - zj[x][1], u2 = zi[2] - zj[x][2];
+                    const float mx = fmaxf(fmaxf(u0, u1), u2);
+                    const float mn = fminf(fminf(u0, u1), u2);
+                    const float md = __builtin_amdgcn_fmed3f(u0, u1, u2);
+                    float g0 = 0.f, g1 = 0.f;
+                    if (mx != md && mn != md) {
+                        const float r = fmaf(wmax, mx - mn, -d);
+                        const float rw = weigh<LOSS>(r, d);
+                        sst = fmaf(r, rw, sst);
+                        if constexpr (GRAD) {
+                            const float h = rw * wmax;
+                            g0 = (u0 == mx) ? h : ((u0 == mn) ? -h : 0.f);
+                            g1 = (u1 == mx) ? h : ((u1 == mn) ? -h : 0.f);
+                        }
+                    } else {
+                        float g[PG];
+                        pair_term<P, LAT, LOSS, GRAD, MASK>(zi, zj[x], d, true, p, D, g, sst);
+                        if constexpr (GRAD) {
+                            g0 = g[0];
+                            g1 = g[1];
+                            const float sum = (g[0] + g[1]) + g[2];
+                            rowacc[2] += sum;
+                            colacc[x][2] += sum;
+                        }
+                    }
+                    if constexpr (GRAD) {
+                        rowacc[0] += g0;
+                        rowacc[1] += g1;
+                        colacc[x][0] += g0;
+                        colacc[x][1] += g1;
+                    }
+                }
+            if constexpr (GRAD) rowacc[PG - 1] = rowacc[PG - 1] - rowacc[0] - rowacc[1];
         } else {
 #pragma unroll
             for (int q = 0; q < NQ; ++q)
@@ -398,6 +446,10 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
     }
 
     if constexpr (GRAD) {
+        if constexpr (P == 3 && LAT == 0 && !MASK) {
+#pragma unroll
+            for (int x = 0; x < CPT; ++x) colacc[x][PG - 1] = colacc[x][PG - 1] - colacc[x][0] - colacc[x][1];
+        }
         // column partials: the 16 row groups hold partial sums of each column
 #pragma unroll
         for (int c = 0; c < PG; ++c) {
