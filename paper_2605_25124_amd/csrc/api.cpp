@@ -465,7 +465,7 @@ gini_status stress_common(gini_ctx* c, const float* Delta, int64_t n, int64_t ld
     D.instcnt = c->cnt;
     D.tile_off = 0;
     D.red_off = 0;
-    const int64_t rblocks = gmds::reduce_block_count(D.n, D.nb, T, pg);
+    const int64_t rblocks = gmds::reduce_block_count(D.n, D.nb, T);
     void* dd = nullptr;
     Slot* sl = nullptr;
     st = upload(c, &D, sizeof D, s, &dd, &sl);
@@ -566,7 +566,7 @@ gini_status make_plan(gini_ctx* c, const gini_instance* inst, int32_t n_inst, in
         D.tile_off = P.prefix[k];
         P.prefix[k + 1] = P.prefix[k] + nt;
         D.red_off = P.rblocks;
-        P.rblocks += gmds::reduce_block_count(D.n, D.nb, T, pg);
+        P.rblocks += gmds::reduce_block_count(D.n, D.nb, T);
         floats += partial_floats(D, T, pg);
         floats = (floats + 63) & ~size_t(63);
     }
@@ -600,7 +600,6 @@ __global__ void k_reset_ctl(gmds::SolveCtl* ctl, uint32_t* ep, int n) {
 gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStream_t s, hipEvent_t ev0 = nullptr,
                      hipEvent_t ev1 = nullptr) {
     const int n_inst = (int)P.desc.size();
-    const int pg = gmds::stored_components(P.p, P.latent);
     // one upload: descriptors, then the tile prefix
     const size_t dbytes = (P.desc.size() * sizeof(InstDesc) + 15) & ~size_t(15);
     std::vector<unsigned char> blob(dbytes + P.prefix.size() * sizeof(int64_t));
@@ -628,7 +627,7 @@ gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStr
                 }
                 ProfScope ps(c, kProfReduce, s, true);
                 GINI_HIP(c, gmds::launch_stress_reduce(ddp + k, 1,
-                                                       gmds::reduce_block_count(P.desc[k].n, P.desc[k].nb, P.T, pg),
+                                                       gmds::reduce_block_count(P.desc[k].n, P.desc[k].nb, P.T),
                                                        P.desc[k].red_off, P.p, P.latent, P.T, gmds::kModeDescent, it,
                                                        s, ps.timer()));
             }

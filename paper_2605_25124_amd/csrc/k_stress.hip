@@ -57,12 +57,11 @@ int units_per_tile(int T) {
     return TileShape<256>::UNITS;
 }
 
-int64_t reduce_block_count(int64_t n, int64_t nb, int T, int pg) {
+int64_t reduce_block_count(int64_t n, int64_t nb, int T) {
     const int64_t cnt = tri_count(nb) * units_per_tile(T) * kWaves;
     int64_t ns = cnt / (kVT * kBatch);
     ns = ns < 1 ? 1 : (ns > kSigSlices ? kSigSlices : ns);
-    const int64_t np = red_points(nb, units_per_tile(T), pg);
-    return ns + (n + np - 1) / np;
+    return ns + (n + kNPT - 1) / kNPT;
 }
 
 hipError_t launch_fill_u32(uint32_t* ptr, int64_t count, uint32_t value, hipStream_t s) {

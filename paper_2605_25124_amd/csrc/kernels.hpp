@@ -91,8 +91,7 @@ hipError_t launch_stress_units(const InstDesc* dd, int n_inst, int64_t count, in
 // is produced; `it` indexes sigma_hist in descent mode.
 hipError_t launch_stress_reduce(const InstDesc* dd, int n_inst, int64_t blocks, int64_t q_base, int p, int latent,
                                 int T, int mode, int it, hipStream_t s, LaunchTimer tm = {});
-// pg: gradient components stored per point (stored_components).
-int64_t reduce_block_count(int64_t n, int64_t nb, int T, int pg);
+int64_t reduce_block_count(int64_t n, int64_t nb, int T);
 int units_per_tile(int T);
 // One launch: all instances, all iterations of the descent.
 hipError_t launch_solve_persistent(const InstDesc* dd, int n_inst, const int64_t* d_unit_prefix,

@@ -21,10 +21,9 @@
 // Reduction.  A unit writes one partial per row (complete for that tile), one
 // partial per column and its stress.  A second launch sums, for every point, the
 // row partials of its tile row and the column partials of its tile column in a
-// fixed order (S interleaved Neumaier sums, S a power of two up to 16 fixed by
-// the instance's tile count, one wave each over 64 consecutive points,
-// combined in index order), and either writes the gradient or takes the
-// descent step.  No floating-point
+// fixed order (sixteen interleaved Neumaier sums, one wave each over 64
+// consecutive points, combined in index order), and either writes the
+// gradient or takes the descent step.  No floating-point
 // atomics anywhere: results are bitwise reproducible and independent of
 // scheduling and of how many instances share a launch.
 #pragma once
@@ -39,7 +38,7 @@ namespace gmds {
 constexpr int kWG = 256;
 constexpr int kLPR = 16;                 // lanes per tile row = one DPP row
 constexpr int kRPS = kWG / kLPR;         // rows per step
-constexpr int kSplit = 16;               // interleaved partial sums per point in the reduction (at most)
+constexpr int kSplit = 16;               // interleaved partial sums per point in the reduction
 constexpr int kBatch = 8;                // loads in flight per stress-slice sum
 constexpr int kWaves = kStressWaves;     // waves per workgroup (one stress partial each)
 static_assert(kWaves * 64 == kWG, "one stress partial per wave");
@@ -514,31 +513,18 @@ __device__ __forceinline__ float loss_factor(const InstDesc& D) {
     return 2.f;
 }
 
-// Loads in flight per partial gradient sum: 16 floats of registers.
-__host__ __device__ constexpr int red_batch(int pg) { return pg >= 8 ? 2 : 16 / pg; }
+// Loads in flight per partial gradient sum: 8 for one or two stored
+// components (more only add masked loads for small instances), fewer for
+// wider gradients to bound the registers.
+__host__ __device__ constexpr int red_batch(int pg) { return pg <= 2 ? 8 : (pg <= 4 ? 4 : 2); }
 
-// Interleaved partial sums per point, S: the fewest (a power of two, at most
-// kSplit) for which every sum takes one batch of loads.  The longest sequence
-// of terms is that of the last tile row, 1 + nb * units.  A reduction group
-// covers kSplit / S runs of kNPT points (kSplit * kNPT partial sums).
-__host__ __device__ inline int red_split(int64_t nb, int units, int pg) {
-    const int64_t need = (1 + nb * units + red_batch(pg) - 1) / red_batch(pg);
-    int sp = 1;
-    while (sp < kSplit && sp < need) sp <<= 1;
-    return sp;
-}
-__host__ __device__ inline int red_points(int64_t nb, int units, int pg) {
-    return kSplit / red_split(nb, units, pg) * kNPT;
-}
-
-// Partial gradient of point k: terms t = s, s + S, ... of the sequence
+// Partial gradient of point k: terms t = s, s + kSplit, ... of the sequence
 // "row partials of its tile row (tiles (b, b..nb-1)), then column partials of
 // its tile column (every unit of tiles (0..b, b))", summed (Neumaier) in
 // increasing t.  The loads of a batch are in flight together; an absent term
 // adds an exact 0.
 template <int P, int LAT, int T>
-__device__ __forceinline__ void point_partial(const InstDesc& D, int64_t k, int s, int S,
-                                              Comp (&acc)[PG_<P, LAT>::value]) {
+__device__ __forceinline__ void point_partial(const InstDesc& D, int64_t k, int s, Comp (&acc)[PG_<P, LAT>::value]) {
     constexpr int PG = PG_<P, LAT>::value;
     constexpr int UNITS = TileShape<T>::UNITS;
     constexpr int RB = red_batch(PG);
@@ -551,11 +537,11 @@ __device__ __forceinline__ void point_partial(const InstDesc& D, int64_t k, int 
     const int nterm = nrow + (int)(b + 1) * UNITS;
     gfl* rbase = gp(D.rowpart) + (tri_index(b, b, nb) * T + kl) * PG;   // row tiles (b, b..) are consecutive
     gfl* cbase = gp(D.colpart) + kl * PG;
-    for (int t0 = s; t0 < nterm; t0 += S * RB) {
+    for (int t0 = s; t0 < nterm; t0 += kSplit * RB) {
         float v[RB][PG];
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
-            const int t = t0 + q * S;
+            const int t = t0 + q * kSplit;
             if (t < nrow) {
 #pragma unroll
                 for (int c = 0; c < PG; ++c) v[q][c] = rbase[t * (T * PG) + c];
@@ -578,54 +564,52 @@ __device__ __forceinline__ void point_partial(const InstDesc& D, int64_t k, int 
     }
 }
 
-// Gradient of the points k0 .. k0 + red_points - 1 (a reduction group): the
-// S partial sums of each point (one wave per partial sum of 64 consecutive
-// points, coalesced loads) are added in index order, scaled by the common
-// factor and applied.  NT is the number of threads executing the call.  LDS:
-// 2 * kSplit * kNPT * PG floats.
+// Gradient of the kNPT points k0 .. k0+kNPT-1: the kSplit partial sums of each
+// point (one wave per partial sum: 64 consecutive points, coalesced loads)
+// are added in index order, scaled by the common factor and applied.  NT is
+// the number of threads executing the call.  LDS: 2 * kSplit * kNPT * PG floats.
 template <int P, int LAT, int T, int NT>
 __device__ void reduce_group(const InstDesc& D, int64_t k0, int mode, float* lds) {
     constexpr int PG = PG_<P, LAT>::value;
-    constexpr int UNITS = TileShape<T>::UNITS;
     const int tid = threadIdx.x;
     const int p = (P == kMaxP) ? D.p : P;
-    const int S = red_split(D.nb, UNITS, PG);
-    const int np = kSplit / S * kNPT;
     // the combining threads fetch what they update before the partial sums
     // arrive, so that its latency overlaps theirs
-    const bool comb = tid < np && k0 + tid < D.n;
+    const bool comb = tid < kNPT && k0 + tid < D.n;
     float zold[P];
     float sc = 1.f;
-    if (mode == kModeGrad) {
-        if (D.grad_out) sc = *D.grad_out;
-    } else if (comb) {
+    if (comb) {
+        if (mode == kModeGrad) {
+            if (D.grad_out) sc = *D.grad_out;
+        } else {
 #pragma unroll
-        for (int c = 0; c < P; ++c) zold[c] = (c < p) ? D.Z[(k0 + tid) * D.ldz + c] : 0.f;
+            for (int c = 0; c < P; ++c) zold[c] = (c < p) ? D.Z[(k0 + tid) * D.ldz + c] : 0.f;
+        }
     }
     for (int item = tid; item < kSplit * kNPT; item += NT) {
-        const int slot = item / kNPT;            // run (slot / S), partial sum (slot % S)
+        const int sp = item / kNPT;
         const int pl = item % kNPT;
-        const int64_t k = k0 + (int64_t)(slot / S) * kNPT + pl;
+        const int64_t k = k0 + pl;
         Comp acc[PG];
-        if (k < D.n) point_partial<P, LAT, T>(D, k, slot % S, S, acc);
+        if (k < D.n) point_partial<P, LAT, T>(D, k, sp, acc);
 #pragma unroll
         for (int c = 0; c < PG; ++c) {
-            lds[((c * kSplit + slot) * kNPT + pl) * 2] = acc[c].hi;
-            lds[((c * kSplit + slot) * kNPT + pl) * 2 + 1] = acc[c].lo;
+            lds[((c * kSplit + sp) * kNPT + pl) * 2] = acc[c].hi;
+            lds[((c * kSplit + sp) * kNPT + pl) * 2 + 1] = acc[c].lo;
         }
     }
     __syncthreads();
-    for (int pt = tid; pt < np; pt += NT) {
-        const int64_t k = k0 + pt;
-        if (k >= D.n) break;
-        const int g = pt / kNPT, pl = pt % kNPT;
+    if (comb) {
+        const int pl = tid;
+        const int64_t k = k0 + pl;
         Comp tot[PG];
 #pragma unroll
         for (int c = 0; c < PG; ++c)
-            for (int q = 0; q < S; ++q) {
+#pragma unroll 4
+            for (int q = 0; q < kSplit; ++q) {
                 Comp x;
-                x.hi = lds[((c * kSplit + g * S + q) * kNPT + pl) * 2];
-                x.lo = lds[((c * kSplit + g * S + q) * kNPT + pl) * 2 + 1];
+                x.hi = lds[((c * kSplit + q) * kNPT + pl) * 2];
+                x.lo = lds[((c * kSplit + q) * kNPT + pl) * 2 + 1];
                 tot[c].add(x);
             }
         float G[P];
@@ -642,10 +626,6 @@ __device__ void reduce_group(const InstDesc& D, int64_t k0, int mode, float* lds
             for (int c = 0; c < P; ++c)
                 if (c < p) D.gradZ[k * D.ldg + c] = sc * G[c];
         } else {
-            if (pt != tid) {
-#pragma unroll
-                for (int c = 0; c < P; ++c) zold[c] = (c < p) ? D.Z[k * D.ldz + c] : 0.f;
-            }
 #pragma unroll
             for (int c = 0; c < P; ++c)
                 if (c < p) D.Z[k * D.ldz + c] = zold[c] - D.eta * G[c];
@@ -788,7 +768,7 @@ constexpr int reduce_lds_floats() {
 // Reduction launch over the concatenated blocks of all instances (block
 // offsets in red_off).  The first blocks of an instance sum one slice of its
 // stress each (with several slices, the last to finish adds them in order);
-// the following blocks take one reduction group (red_points points) each.
+// the following blocks take kNPT points each.
 template <int P, int LAT, int T>
 __global__ __launch_bounds__(kRedWG) void k_stress_reduce(const InstDesc* __restrict__ dd, int n_inst,
                                                           int64_t q_base, int mode, int it) {
@@ -834,7 +814,7 @@ __global__ __launch_bounds__(kRedWG) void k_stress_reduce(const InstDesc* __rest
         return;
     }
     if (mode == kModeSigma) return;
-    reduce_group<P, LAT, T, kRedWG>(D, (b - ns) * red_points(D.nb, TileShape<T>::UNITS, PG), mode, lds);
+    reduce_group<P, LAT, T, kRedWG>(D, (b - ns) * kNPT, mode, lds);
 }
 
 // Persistent solver.  Queue item q = (iteration it, instance k, local unit),
@@ -922,8 +902,7 @@ __global__ __launch_bounds__(kWG) void k_solve_persistent(const InstDesc* __rest
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             const Comp s = instance_sigma<T, kWG>(D, lds);
             write_sigma(D, kModeDescent, it, s);
-            const int64_t np = red_points(D.nb, UNITS, PG);
-            for (int64_t k0 = 0; k0 < D.n; k0 += np) reduce_group<P, LAT, T, kWG>(D, k0, kModeDescent, lds);
+            for (int64_t k0 = 0; k0 < D.n; k0 += kNPT) reduce_group<P, LAT, T, kWG>(D, k0, kModeDescent, lds);
             __threadfence();
             __syncthreads();
             if (tid == 0) {
