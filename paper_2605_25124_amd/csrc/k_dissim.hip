@@ -193,7 +193,8 @@ __global__ __launch_bounds__(kDWG) void k_dissim_lane(DissimArgs A, int nu0, int
             tie = tie || ((k < m) && (v[k] == v[k - 1]));
         });
         // untied positions: t = 2k + 2, weight index 2k, the same for every lane
-#pragma unroll
+        // (scalar loads; one nu at a time keeps them within the SGPR budget)
+#pragma unroll 1
         for (int q = 0; q < kNuChunk; ++q) {
             if (q < nq) {
                 const float* U = A.wtab + (int64_t)(nu0 + q) * wlen;
@@ -329,11 +330,17 @@ __global__ __launch_bounds__(kDWG) void k_dissim_group(DissimArgs A, int nu0, in
         for (int ti = tid; ti < wlen; ti += kDWG)
             wt[q * wstride + wskew<E>(ti)] = A.wtab[(int64_t)(nu0 + q) * wlen + ti];
     __syncthreads();
-    const int g = tid % G;
+    const int g0 = tid % G;
     const int grp = tid / G;
     const float inf = __builtin_inff();
 #pragma unroll 1
     for (int pq = grp; pq < TS * TS; pq += NG) {
+        // g is made opaque at every pair, so that the compiler recomputes the
+        // per-stage lane masks of the sort where they are used instead of
+        // keeping some sixty of them live across the loop (SGPR spills and
+        // one wave less per SIMD)
+        int g = g0;
+        asm volatile("" : "+v"(g));
         const int r = pq / TS, c = pq % TS;
         const int64_t i = I * TS + r, j = J * TS + c;
         const bool valid = (i < n) && (j < n) && (I < J || r < c);
