@@ -155,24 +155,30 @@ __global__ __launch_bounds__(kDWG) void k_dissim_lane(DissimArgs A, int nu0, int
     constexpr int TS = 32;
     __shared__ float xs[2 * TS * 65];
     __shared__ float out[kNuChunk * TS * (TS + 1)];
-    const int m = A.m;
-    const int S = m | 1;                                // odd LDS row stride: no bank conflicts
+    const int m0 = A.m;
+    const int S = m0 | 1;                               // odd LDS row stride: no bank conflicts
     const int64_t n = A.n;
     const int64_t nb = (n + TS - 1) / TS;
     int64_t I, J;
     tri_decode(blockIdx.x, nb, I, J);
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < 2 * TS * m; idx += kDWG) {
-        const int row = idx / m, c = idx % m;
+    for (int idx = tid; idx < 2 * TS * m0; idx += kDWG) {
+        const int row = idx / m0, c = idx % m0;
         const int64_t g = (row < TS) ? (I * TS + row) : (J * TS + row - TS);
         xs[row * S + c] = (g < n) ? A.X[g * A.ldx + c] : 0.f;
     }
     __syncthreads();
     const int c = tid % TS;
     const float inf = __builtin_inff();
-    const int wlen = 2 * m - 1;
+    const int wlen = 2 * m0 - 1;
 #pragma unroll 1
     for (int sidx = 0; sidx < TS * TS / kDWG; ++sidx) {
+        // m is made opaque at every pair row (and every nu below), so that the
+        // wave-uniform tests k < m of the unrolled loops are formed where they
+        // are used instead of being kept live across the loops (hundreds of
+        // SGPRs, spilled)
+        int m = m0;
+        asm volatile("" : "+s"(m));
         const int r = tid / TS + sidx * (kDWG / TS);
         const int64_t i = I * TS + r, j = J * TS + c;
         const bool valid = (i < n) && (j < n) && (I < J || r < c);
@@ -196,6 +202,7 @@ __global__ __launch_bounds__(kDWG) void k_dissim_lane(DissimArgs A, int nu0, int
         // (scalar loads; one nu at a time keeps them within the SGPR budget)
 #pragma unroll 1
         for (int q = 0; q < kNuChunk; ++q) {
+            asm volatile("" : "+s"(m));
             if (q < nq) {
                 const float* U = A.wtab + (int64_t)(nu0 + q) * wlen;
                 float acc[4] = {0.f, 0.f, 0.f, 0.f};
@@ -211,6 +218,7 @@ __global__ __launch_bounds__(kDWG) void k_dissim_lane(DissimArgs A, int nu0, int
                 // With ties the lane recomputes the sum run by run: a run a..b
                 // of equal values z contributes (b-a+1) z W[a+b+2].
                 for (int q = 0; q < nq; ++q) {
+                    asm volatile("" : "+s"(m));
                     const float* W = A.wtab + (int64_t)(nu0 + q) * wlen;
                     int rs = 0;
                     float acc = 0.f;
