@@ -247,24 +247,33 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
     float* red = zcol + T * P;
 
     // Delta loads for one step of the unit (unmasked: 16-byte global loads)
+    // Masked tiles (the diagonal, and the last tile row or column) decide
+    // validity in 32-bit tile-local coordinates: pair (il, jl) exists if
+    // il < rows_left, jl < cols_left and, on a diagonal tile, jl > il.  Off
+    // the diagonal every column lies above every row.
+    const int rows_left = (int)min<int64_t>(n - I * T, (int64_t)T);
+    const int cols_left = (int)min<int64_t>(n - j0, (int64_t)T);
+    const bool diag = (I == J);
     auto load_step = [&](int s, f4v (&buf)[NQ]) {
         const int64_t i = i0 + s * kRPS + rr;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            const int64_t jb = j0 + 4 * (c4 + q * kLPR);
             if constexpr (!MASK) {
+                const int64_t jb = j0 + 4 * (c4 + q * kLPR);
                 buf[q] = *(gf4*)(D.Delta + i * D.ldd + jb);
             } else {
+                const int il = sub * UR + s * kRPS + rr;
+                const int jbl = 4 * (c4 + q * kLPR);
                 f4v v = {0.f, 0.f, 0.f, 0.f};
-                if (i < n && jb + 3 > i && jb < n) {
-                    const float* Dr = D.Delta + i * D.ldd;
-                    if (D.vec && jb + 3 < n) {
-                        v = *(gf4*)(Dr + jb);
+                if (il < rows_left && jbl < cols_left && (!diag || jbl + 3 > il)) {
+                    const float* Dr = D.Delta + i * D.ldd + j0;
+                    if (D.vec && jbl + 3 < cols_left) {
+                        v = *(gf4*)(Dr + jbl);
                     } else {
-                        if (jb + 0 < n && jb + 0 > i) v.x = gp(Dr)[jb + 0];
-                        if (jb + 1 < n && jb + 1 > i) v.y = gp(Dr)[jb + 1];
-                        if (jb + 2 < n && jb + 2 > i) v.z = gp(Dr)[jb + 2];
-                        if (jb + 3 < n && jb + 3 > i) v.w = gp(Dr)[jb + 3];
+                        if (jbl + 0 < cols_left && (!diag || jbl + 0 > il)) v.x = gp(Dr)[jbl + 0];
+                        if (jbl + 1 < cols_left && (!diag || jbl + 1 > il)) v.y = gp(Dr)[jbl + 1];
+                        if (jbl + 2 < cols_left && (!diag || jbl + 2 > il)) v.z = gp(Dr)[jbl + 2];
+                        if (jbl + 3 < cols_left && (!diag || jbl + 3 > il)) v.w = gp(Dr)[jbl + 3];
                     }
                 }
                 buf[q] = v;
@@ -415,8 +424,8 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int x = q * 4 + e;
-                    const int64_t j = j0 + 4 * (c4 + q * kLPR) + e;
-                    const bool valid = !MASK || ((j > i) && (j < n) && (i < n));
+                    const int jl = 4 * (c4 + q * kLPR) + e;
+                    const bool valid = !MASK || ((il < rows_left) && (jl < cols_left) && (!diag || jl > il));
                     float g[PG];
                     pair_term<P, LAT, LOSS, GRAD, MASK>(zi, zj[x], buf[q][e], valid, p, D, g, sst);
                     if constexpr (GRAD) {
@@ -432,7 +441,7 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
 #pragma unroll
             for (int c = 0; c < PG; ++c) {
                 const float tot = row16_sum(rowacc[c]);
-                if (c4 == 0 && (!MASK || i < n)) gpw(D.rowpart)[(lt * T + il) * PG + c] = tot;
+                if (c4 == 0 && (!MASK || il < rows_left)) gpw(D.rowpart)[(lt * T + il) * PG + c] = tot;
             }
         }
         sig.add(sst);
@@ -751,8 +760,22 @@ __device__ __forceinline__ int find_instance(const InstDesc* dd, int n_inst, int
     return lo;
 }
 
+// Waves per SIMD asked of the register allocator: the raw stress with the
+// Gini latent at p = 2 and p = 3 on 128-wide tiles.  The masked path of the
+// edge and diagonal tiles sets the register count (88 and 153 against 75 and
+// 114 for the interior path); under the cap the allocator spills a few
+// registers instead (16 and 104 bytes per lane), and the extra wave per SIMD
+// pays for it (about 3 % and 7 %).  The Sammon kernels would spill more, so
+// they keep the default.
+template <int P, int LAT, int LOSS, int T>
+constexpr int units_waves() {
+    if (LOSS != kLossRaw || T != 128 || LAT != 0) return 1;
+    return P == 2 ? 6 : (P == 3 ? 4 : 1);
+}
+
 template <int P, int LAT, int LOSS, int T, bool GRAD>
-__global__ __launch_bounds__(kWG) void k_stress_units(const InstDesc* __restrict__ dd, int n_inst, int64_t q_base) {
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(units_waves<P, LAT, LOSS, T>())))
+void k_stress_units(const InstDesc* __restrict__ dd, int n_inst, int64_t q_base) {
     __shared__ float lds[unit_lds_floats<P, T>()];
     const int64_t q = (int64_t)blockIdx.x + q_base;
     const int k = find_instance(dd, n_inst, q);
