@@ -328,7 +328,6 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
 
     auto compute_step = [&](int s, const f4v (&buf)[NQ]) {
         const int il = sub * UR + s * kRPS + rr;           // row within the tile
-        const int64_t i = I * T + il;
         float zi[P];
 #pragma unroll
         for (int c = 0; c < P; ++c) zi[c] = zrow[(s * kRPS + rr) * P + c];
