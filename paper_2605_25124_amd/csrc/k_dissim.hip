@@ -319,8 +319,15 @@ __device__ __forceinline__ int wskew(int ti) {
     return ti + ti / (2 * E);
 }
 
+// G = 32, E = 32 (m in (512, 1024]) is asked for 5 waves per SIMD: 96
+// registers with a few spilled (72 bytes per lane) measure 3 % faster than
+// 126 registers at 4 waves.
 template <int G, int E>
-__global__ __launch_bounds__(kDWG) void k_dissim_group(DissimArgs A, int nu0, int nq) {
+constexpr int dissim_group_waves() { return (G == 32 && E == 32) ? 5 : 1; }
+
+template <int G, int E>
+__global__ __launch_bounds__(kDWG) __attribute__((amdgpu_waves_per_eu(dissim_group_waves<G, E>())))
+void k_dissim_group(DissimArgs A, int nu0, int nq) {
     constexpr int TS = 16;
     constexpr int NG = kDWG / G;
     extern __shared__ float dyn[];
