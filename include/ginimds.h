@@ -51,7 +51,7 @@ typedef enum {
     GINI_ENOMEM = 2,        /* device or host allocation failed              */
     GINI_EDEVICE = 3,       /* HIP runtime error, or a device-side failure   */
     GINI_ENOTFINITE = 4,    /* a result was not finite (checked solves only) */
-    GINI_EUNSUPPORTED = 5   /* valid but outside what this build supports    */
+    GINI_EUNSUPPORTED = 5   /* valid but outside what the library supports  */
 } gini_status;
 
 /* Distance used between latent points.  GINI: the generalised Gini
