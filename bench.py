@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-select", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the Sammon-loss and classical-MDS measurements on the image workload")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--mode", choices=["auto", "persistent", "batched"], default="auto")
     ap.add_argument("--tile", type=int, default=256)
@@ -183,6 +185,45 @@ def main():
             "reduce_avg_us": round(prof["reduce_ms"] * 1e3 / max(prof["reduce_launches"], 1), 2)}
     log(f"roofline {kname}: {avg_ms * 1e3:.1f} us/launch -> {achieved:.0f} GB/s")
 
+    # ---- the Sammon loss and classical MDS on the same Delta (n = 10^4)
+    extras = None
+    if not args.no_extras:
+        ds = gm.gini_sum(D)
+        eta = gm.gini_sammon_step(D, p, nu)
+        def sammon_inst(Zs):
+            return gm.Instance(D, Zs, nu, gm.LATENT_GINI, eta, None, None, None, gm.LOSS_SAMMON, ds)
+        ks = 100
+        gm.gini_mds_solve([sammon_inst(Z0.clone())], 5, gm.SOLVE_BATCHED, best["tile"])
+        torch.cuda.synchronize()
+        Zs = Z0.clone()
+        t0 = time.perf_counter()
+        gm.gini_mds_solve([sammon_inst(Zs)], ks, gm.SOLVE_BATCHED, best["tile"])
+        torch.cuda.synchronize()
+        t_sam = (time.perf_counter() - t0) / ks
+        gm.gini_profile_enable(0, True)
+        gm.gini_mds_solve([sammon_inst(Z0.clone())], ks, gm.SOLVE_BATCHED, best["tile"])
+        torch.cuda.synchronize()
+        prof_s = gm.gini_profile_read(0)
+        gm.gini_profile_enable(0, False)
+        sam_us = prof_s["tile_ms"] / max(1, prof_s["tile_launches"]) * 1e3
+        gm.gini_classical_mds(D[:512, :512].contiguous(), p)            # warm the workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, ev, cm_iters = gm.gini_classical_mds(D, p)
+        torch.cuda.synchronize()
+        t_cm = time.perf_counter() - t0
+        extras = {
+            "sammon": {"workload": f"images n={n}, nu=2, p=2 Gini latent, Sammon stress, {ks} descent steps",
+                       "ms_per_step": round(t_sam * 1e3, 5), "pair_evals_per_s": round(pairs / t_sam, 1),
+                       "units_avg_us": round(sam_us, 2),
+                       "units_gbs_algorithmic": round(alg_bytes / (sam_us * 1e-6) / 1e9, 1)},
+            "classical_mds": {"workload": f"images n={n}, nu=2 Delta, p=2, subspace iteration",
+                              "seconds": round(t_cm, 4), "iterations": cm_iters,
+                              "delta_pass_gbs": round(cm_iters * 4.0 * n * n / t_cm / 1e9, 1),
+                              "eigenvalues": [round(float(v), 3) for v in ev]}}
+        log(f"sammon {t_sam * 1e6:.1f} us/step (units {sam_us:.1f} us); classical MDS {t_cm * 1e3:.1f} ms, "
+            f"{cm_iters} iterations")
+
     # ---- nu-sweep: batched persistent vs plain
     sweep = None
     if not args.no_sweep:
@@ -287,7 +328,7 @@ def main():
                       "parallelism": "single GPU"},
            "hbm_gbs_algorithmic": round(achieved, 1),
            "dissim_build_s": round(dissim_s, 4),
-           "roofline": roof, "sweep": sweep, "select": select, "cpu_baseline": cpu}
+           "roofline": roof, "sweep": sweep, "select": select, "extras": extras, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
 

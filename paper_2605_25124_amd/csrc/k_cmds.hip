@@ -16,46 +16,63 @@ namespace {
 constexpr int kCW = 256;           // threads of a row workgroup
 constexpr int kQ = kMaxCmdsQ;      // widest block handled
 
-// out[i, c] = sum_j Delta_ij^2 V[j, c], j != i (full rows of Delta); one
-// workgroup per row.
+// out[i, c] = sum_j Delta_ij^2 V[j, c], j != i (full rows of Delta).  A
+// workgroup takes kRows consecutive rows, so that every element of V it loads
+// serves kRows rows (V is read from L2 n / kRows times per pass instead of n).
+// Each row's sum has the same shape as with one row per workgroup: thread t
+// adds j = t, t + kCW, ... in order (compensated), then a fixed tree over the
+// threads.
+constexpr int kRows = 4;
+
 __global__ __launch_bounds__(kCW) void k_d2v(const float* __restrict__ Delta, int64_t n, int64_t ldd,
                                              const float* __restrict__ V, int q, float* __restrict__ out) {
     __shared__ float lds[2 * kCW * kQ];
-    const int64_t i = blockIdx.x;
-    const float* row = Delta + i * ldd;
-    Comp acc[kQ];
+    const int64_t i0 = (int64_t)blockIdx.x * kRows;
+    const int nr = (int)min<int64_t>(kRows, n - i0);
+    Comp acc[kRows][kQ];
     for (int64_t j = threadIdx.x; j < n; j += kCW) {
-        if (j == i) continue;
-        const float d = row[j];
-        const float d2 = d * d;
+        float vj[kQ];
 #pragma unroll
-        for (int c = 0; c < kQ; ++c)
-            if (c < q) acc[c].add(d2 * V[j * q + c]);
+        for (int c = 0; c < kQ; ++c) vj[c] = (c < q) ? V[j * q + c] : 0.f;
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            if (r >= nr || j == i0 + r) continue;
+            const float d = Delta[(i0 + r) * ldd + j];
+            const float d2 = d * d;
+#pragma unroll
+            for (int c = 0; c < kQ; ++c)
+                if (c < q) acc[r][c].add(d2 * vj[c]);
+        }
     }
     const int t = threadIdx.x;
 #pragma unroll
-    for (int c = 0; c < kQ; ++c) {
-        lds[(c * kCW + t) * 2] = acc[c].hi;
-        lds[(c * kCW + t) * 2 + 1] = acc[c].lo;
-    }
-    __syncthreads();
-    for (int st = kCW / 2; st > 0; st >>= 1) {
-        if (t < st) {
+    for (int r = 0; r < kRows; ++r) {
+        if (r >= nr) break;                    // nr is the same for the whole workgroup
 #pragma unroll
-            for (int c = 0; c < kQ; ++c) {
-                Comp a, b;
-                a.hi = lds[(c * kCW + t) * 2];
-                a.lo = lds[(c * kCW + t) * 2 + 1];
-                b.hi = lds[(c * kCW + t + st) * 2];
-                b.lo = lds[(c * kCW + t + st) * 2 + 1];
-                a.add(b);
-                lds[(c * kCW + t) * 2] = a.hi;
-                lds[(c * kCW + t) * 2 + 1] = a.lo;
-            }
+        for (int c = 0; c < kQ; ++c) {
+            lds[(c * kCW + t) * 2] = acc[r][c].hi;
+            lds[(c * kCW + t) * 2 + 1] = acc[r][c].lo;
         }
         __syncthreads();
+        for (int st = kCW / 2; st > 0; st >>= 1) {
+            if (t < st) {
+#pragma unroll
+                for (int c = 0; c < kQ; ++c) {
+                    Comp a, b;
+                    a.hi = lds[(c * kCW + t) * 2];
+                    a.lo = lds[(c * kCW + t) * 2 + 1];
+                    b.hi = lds[(c * kCW + t + st) * 2];
+                    b.lo = lds[(c * kCW + t + st) * 2 + 1];
+                    a.add(b);
+                    lds[(c * kCW + t) * 2] = a.hi;
+                    lds[(c * kCW + t) * 2 + 1] = a.lo;
+                }
+            }
+            __syncthreads();
+        }
+        if (t < q) out[(i0 + r) * q + t] = lds[(t * kCW) * 2] + lds[(t * kCW) * 2 + 1];
+        __syncthreads();
     }
-    if (t < q) out[i * q + t] = lds[(t * kCW) * 2] + lds[(t * kCW) * 2 + 1];
 }
 
 // Partial sums over a block of rows of A^T B (qa x qb entries, compensated,
@@ -135,7 +152,7 @@ __global__ __launch_bounds__(kCW) void k_rowmat(const float* __restrict__ A, int
 
 hipError_t launch_d2v(const float* Delta, int64_t n, int64_t ldd, const float* V, int q, float* out,
                       hipStream_t s) {
-    hipLaunchKernelGGL(k_d2v, dim3((unsigned)n), dim3(kCW), 0, s, Delta, n, ldd, V, q, out);
+    hipLaunchKernelGGL(k_d2v, dim3((unsigned)((n + kRows - 1) / kRows)), dim3(kCW), 0, s, Delta, n, ldd, V, q, out);
     return hipGetLastError();
 }
 
