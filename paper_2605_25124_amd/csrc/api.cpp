@@ -1461,12 +1461,7 @@ gini_status gini_classical_mds(gini_ctx* c, const float* Delta, int64_t n, int64
         // Yh = B V = -1/2 H (D^2 V)
         GINI_HIP(c, gmds::launch_d2v(Delta, n, ldd, V, q, Yp, s));
         GINI_HIP(c, gmds::launch_gram(Yp, q, nullptr, 1, n, part, gout, s));
-        std::vector<double> cs;
-        st = fetch(q, cs);
-        if (st != GINI_OK) return st;
-        for (auto& v : cs) v /= (double)n;
-        st = put(shift, cs);
-        if (st != GINI_OK) return st;
+        GINI_HIP(c, gmds::launch_colmean(gout, q, n, shift, s));      // centring stays on the device
         GINI_HIP(c, gmds::launch_rowmat(Yp, q, shift, -0.5f, Idev, q, n, Yh, q, s));
         // Rayleigh-Ritz on span(V): T = V^T B V
         GINI_HIP(c, gmds::launch_gram(V, q, Yh, q, n, part, gout, s));

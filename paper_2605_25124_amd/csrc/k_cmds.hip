@@ -148,7 +148,18 @@ __global__ __launch_bounds__(kCW) void k_rowmat(const float* __restrict__ A, int
     }
 }
 
+// shift[c] = (hi + lo) / n of the compensated column sums (hi, lo) in sums.
+__global__ void k_colmean(const float* __restrict__ sums, int q, int64_t n, float* __restrict__ shift) {
+    const int c = threadIdx.x;
+    if (c < q) shift[c] = (float)(((double)sums[2 * c] + (double)sums[2 * c + 1]) / (double)n);
+}
+
 }  // namespace
+
+hipError_t launch_colmean(const float* sums, int q, int64_t n, float* shift, hipStream_t s) {
+    hipLaunchKernelGGL(k_colmean, dim3(1), dim3(64), 0, s, sums, q, n, shift);
+    return hipGetLastError();
+}
 
 hipError_t launch_d2v(const float* Delta, int64_t n, int64_t ldd, const float* V, int q, float* out,
                       hipStream_t s) {

@@ -121,6 +121,8 @@ hipError_t launch_gram(const float* A, int qa, const float* B, int qb, int64_t n
                        hipStream_t s);
 // out[i, :] = (alpha (A[i, :] - shift)) M; M qa x qb row-major (device),
 // shift (qa, device) may be null.
+// shift[c] = (sums[2c] + sums[2c+1]) / n, c < q <= 64 (column means from launch_gram's output).
+hipError_t launch_colmean(const float* sums, int q, int64_t n, float* shift, hipStream_t s);
 hipError_t launch_rowmat(const float* A, int qa, const float* shift, float alpha, const float* M, int qb, int64_t n,
                          float* out, int64_t ldo, hipStream_t s);
 
