@@ -59,7 +59,7 @@ int units_per_tile(int T) {
 
 int64_t reduce_block_count(int64_t n, int64_t nb, int T) {
     const int64_t cnt = tri_count(nb) * units_per_tile(T) * kWaves;
-    int64_t ns = cnt / (kVT * kBatch);
+    int64_t ns = (cnt + kVT * kBatch - 1) / (kVT * kBatch);
     ns = ns < 1 ? 1 : (ns > kSigSlices ? kSigSlices : ns);
     return ns + (n + kNPT - 1) / kNPT;
 }

@@ -652,11 +652,12 @@ template <int T>
 __device__ __forceinline__ int64_t sigma_count(const InstDesc& D) {
     return tri_count(D.nb) * TileShape<T>::UNITS * kWaves;
 }
-// About kVT * kBatch partials per slice, at most kSigSlices (one slice --
-// written directly, no combining step -- for small instances).
+// At most kVT * kBatch partials per slice (one batch of loads per virtual
+// thread), at most kSigSlices slices (one slice -- written directly, no
+// combining step -- for small instances).
 template <int T>
 __device__ __forceinline__ int sigma_slices(const InstDesc& D) {
-    const int64_t s = sigma_count<T>(D) / (kVT * kBatch);
+    const int64_t s = (sigma_count<T>(D) + kVT * kBatch - 1) / (kVT * kBatch);
     return (int)(s < 1 ? 1 : (s > kSigSlices ? kSigSlices : s));
 }
 
@@ -695,7 +696,11 @@ __device__ Comp sigma_slice(const InstDesc& D, int slice, float* lds) {
         lds[kVT + vt] = acc.lo;
     }
     __syncthreads();
-    for (int st = kVT / 2; st > 0; st >>= 1) {
+    // The tree's last six levels (64 values) take one wave and its shuffles
+    // when every value has a thread of its own (the same additions in the
+    // same order as through LDS, without a barrier per level).
+    constexpr int STW = (NT >= kVT) ? 64 : 1;
+    for (int st = kVT / 2; st >= STW; st >>= 1) {
         for (int x = threadIdx.x; x < st; x += NT) {
             Comp u;
             u.hi = lds[x];
@@ -706,6 +711,24 @@ __device__ Comp sigma_slice(const InstDesc& D, int slice, float* lds) {
             u.add(w);
             lds[x] = u.hi;
             lds[kVT + x] = u.lo;
+        }
+        __syncthreads();
+    }
+    if constexpr (NT >= kVT) {
+        if (threadIdx.x < 64) {
+            Comp u;
+            u.hi = lds[threadIdx.x];
+            u.lo = lds[kVT + threadIdx.x];
+            for (int st = 32; st > 0; st >>= 1) {
+                Comp w;
+                w.hi = __shfl_down(u.hi, st, 64);
+                w.lo = __shfl_down(u.lo, st, 64);
+                u.add(w);
+            }
+            if (threadIdx.x == 0) {
+                lds[0] = u.hi;
+                lds[kVT] = u.lo;
+            }
         }
         __syncthreads();
     }
