@@ -234,6 +234,33 @@ void orc_dissim_pairs(const double* X, int m, int64_t ldx, int mode, const int64
     free(z);
 }
 
+/* Rounding scale of each dissimilarity, used by the tests' tolerances.  The
+ * symmetrised distance is piecewise linear and homogeneous of degree one in z
+ * (Section III-B), so with both rank vectors frozen D = sum_c z_c g_c, g its
+ * gradient (orc_sym; Euler's identity).  S_ij = sum_c |z_c g_c| is the sum of
+ * the absolute values of the terms whose sum is D_ij: S_ij >= |D_ij|, with
+ * equality when no two terms differ in sign.  Full matrix, zero diagonal. */
+void orc_dissim_scale(const double* X, int64_t n, int m, int64_t ldx, int mode, double nu,
+                      double* S, int64_t lds) {
+    double* z = (double*)malloc(sizeof(double) * (size_t)m);
+    double* g = (double*)malloc(sizeof(double) * (size_t)m);
+    orc_gini_ws w;
+    orc_ws_init(&w, m, nu);
+    for (int64_t i = 0; i < n; ++i) {
+        S[i * lds + i] = 0.0;
+        for (int64_t j = i + 1; j < n; ++j) {
+            for (int c = 0; c < m; ++c) z[c] = orc_diff(X[i * ldx + c], X[j * ldx + c], mode);
+            orc_sym(z, &w, g);
+            double a = 0.0;
+            for (int c = 0; c < m; ++c) a += fabs(z[c] * g[c]);
+            S[i * lds + j] = a;
+            S[j * lds + i] = a;
+        }
+    }
+    orc_ws_free(&w);
+    free(z); free(g);
+}
+
 /* ------------------------------------------------------------ the stress */
 
 /* Latent distance and its gradient d delta / d u for u = Z_i - Z_j (R4, R6). */
@@ -312,6 +339,41 @@ double orc_grad_rows(const double* Drows, int64_t ldr, const int64_t* rows, int6
     free(u); free(a);
     orc_ws_free(&w);
     return part;
+}
+
+/* Rounding scale of the gradient, used by the tests' tolerances: for each
+ * selected point i and coordinate c, the sum over j != i of the absolute
+ * values of the terms whose sum is G_ic -- |2 r_ij a_c| for the raw stress
+ * (loss 0, as in orc_stress), |2 r_ij a_c| / (S Delta_ij) for Sammon's stress
+ * (loss 1, as in orc_sammon, with S its normaliser passed by the caller and
+ * no term for Delta_ij <= 0).  B_ic >= |G_ic|, with equality when the terms
+ * of (i, c) share one sign.  Row i of Delta is read from Drows[q*ldr + j]. */
+void orc_grad_scale_rows(const double* Drows, int64_t ldr, const int64_t* rows, int64_t nrows, int64_t n,
+                         const double* Z, int p, int64_t ldz, double nu, int latent, int mode, int loss,
+                         double S, double* B, int64_t ldb) {
+    orc_gini_ws w;
+    orc_ws_init(&w, p, nu);
+    double* u = (double*)malloc(sizeof(double) * (size_t)p);
+    double* a = (double*)malloc(sizeof(double) * (size_t)p);
+    for (int64_t q = 0; q < nrows; ++q) {
+        int64_t i = rows[q];
+        for (int c = 0; c < p; ++c) B[q * ldb + c] = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double d = Drows[q * ldr + j];
+            if (loss == 1 && !(d > 0.0)) continue;
+            for (int c = 0; c < p; ++c) u[c] = orc_diff(Z[i * ldz + c], Z[j * ldz + c], mode);
+            double delta = orc_latent(u, p, latent, &w, a);
+            double r = delta - d;
+            for (int c = 0; c < p; ++c) {
+                double t = 2.0 * r * a[c];
+                if (loss == 1) t = t / d / S;
+                B[q * ldb + c] += fabs(t);
+            }
+        }
+    }
+    free(u); free(a);
+    orc_ws_free(&w);
 }
 
 /* R7: default step for fixed-step gradient descent on the raw stress. */

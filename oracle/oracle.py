@@ -74,6 +74,8 @@ def lib():
         L.orc_sammon_step.argtypes = [P, i64, i64, i32, f64, i32]
         L.orc_sammon_step.restype = f64
         L.orc_solve_sammon.argtypes = [P, i64, i64, P, i32, i64, f64, i32, i32, i32, f64, P]
+        L.orc_dissim_scale.argtypes = [P, i64, i32, i64, i32, f64, P, i64]
+        L.orc_grad_scale_rows.argtypes = [P, i64, P, i64, i64, P, i32, i64, f64, i32, i32, i32, f64, P, i64]
         _lib = L
     return _lib
 
@@ -262,6 +264,39 @@ def standardize(X):
     sd = X.std(axis=0)
     sd = np.where(sd > 0, sd, 1.0)
     return (X - np.median(X, axis=0)) / sd
+
+
+def dissim_scale(X, nu: float, mode: int = MATCH32) -> np.ndarray:
+    """S_ij = sum_c |z_c g_c| (g the rank-frozen gradient of the distance): the
+    sum of the absolute values of the terms whose sum is Delta_ij, the scale
+    of its rounding error.  Full n x n matrix."""
+    X = _f64(X)
+    n, m = X.shape
+    S = np.empty((n, n), dtype=np.float64)
+    lib().orc_dissim_scale(_ptr(X), n, m, m, mode, float(nu), _ptr(S), n)
+    return S
+
+
+def grad_scale_rows(Drows, rows, Z, nu: float, latent: int = LATENT_GINI, mode: int = MATCH32,
+                    loss: int = 0, S: float = 0.0) -> np.ndarray:
+    """B[q, c] = sum_{j != rows[q]} |term_j| over the terms whose sum is the
+    gradient entry G[rows[q], c]: |2 r a_c| for the raw stress (loss 0), that
+    over S Delta_ij for Sammon's stress (loss 1, S its normaliser)."""
+    D = _f64(Drows)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    Z = _f64(Z)
+    n, p = Z.shape
+    B = np.empty((rows.shape[0], p), dtype=np.float64)
+    lib().orc_grad_scale_rows(_ptr(D), D.shape[1], _ptr(rows), rows.shape[0], n, _ptr(Z), p, p, float(nu),
+                              latent, mode, int(loss), float(S), _ptr(B), p)
+    return B
+
+
+def grad_scale(Delta, Z, nu: float, latent: int = LATENT_GINI, mode: int = MATCH32, loss: int = 0,
+               S: float = 0.0) -> np.ndarray:
+    """grad_scale_rows over every point (Delta n x n)."""
+    n = np.asarray(Z).shape[0]
+    return grad_scale_rows(Delta, np.arange(n), Z, nu, latent, mode, loss, S)
 
 
 def grad_rows(Drows, rows, Z, nu: float, latent: int = LATENT_GINI, mode: int = MATCH32):

@@ -509,3 +509,93 @@ def test_standardize_properties(orc):
     Xs = X / X.std(axis=0)
     np.testing.assert_allclose(orc.dissim(Y, [2.0], orc.EXACT), orc.dissim(Xs, [2.0], orc.EXACT), rtol=1e-12,
                                atol=1e-12)
+
+
+# ------------------------------------------- rounding scales of the tolerances
+@pytest.mark.parametrize("nu", [1.5, 2.0, 3.7])
+def test_dissim_scale_bounds_and_homogeneity(orc, nu):
+    """S_ij is a sum of absolute values of terms whose sum is Delta_ij:
+    S >= |Delta| everywhere, symmetric, zero on the diagonal, and 1-homogeneous
+    (ranks do not change under scaling by a positive power of two)."""
+    X, _ = _problem(31, 25, 9, 2)
+    S = orc.dissim_scale(X, nu, orc.EXACT)
+    D = orc.dissim(X, [nu], orc.EXACT)[0]
+    assert np.all(S >= np.abs(D) * (1 - 1e-12))
+    assert np.array_equal(S, S.T) and np.all(np.diag(S) == 0.0)
+    np.testing.assert_allclose(orc.dissim_scale(4.0 * X, nu, orc.EXACT), 4.0 * S, rtol=1e-13)
+    # with ties (integer data) as well
+    Xt = np.round(X)
+    St = orc.dissim_scale(Xt, nu, orc.EXACT)
+    if nu == 2.0:
+        assert np.all(St >= np.abs(orc.dissim(Xt, [nu], orc.EXACT)[0]) * (1 - 1e-12))
+
+
+def test_dissim_scale_closed_forms(orc):
+    """At nu = 2 the distance is half the Gini mean difference, whose
+    rank-free derivative is g_c = (#{b: z_b < z_c} - #{b: z_b > z_c}) / 2.
+    z = (1, 2, 3, 4): g = (-3/2, -1/2, 1/2, 3/2), Delta = 5, S = 10.
+    z = (-3, -1, 2, 5): every z_c g_c >= 0, so S = Delta = 13.5."""
+    for z, s_ref, d_ref in (([1.0, 2.0, 3.0, 4.0], 10.0, 5.0), ([-3.0, -1.0, 2.0, 5.0], 13.5, 13.5)):
+        X = np.array([z, [0.0, 0.0, 0.0, 0.0]])
+        S = orc.dissim_scale(X, 2.0, orc.EXACT)
+        D = orc.dissim(X, [2.0], orc.EXACT)[0]
+        assert S[0, 1] == pytest.approx(s_ref, rel=1e-14)
+        assert D[0, 1] == pytest.approx(d_ref, rel=1e-14)
+    # the no-cancellation case holds at any nu: negative z exactly on the low ranks
+    X = np.array([[-3.0, -1.0, 2.0, 5.0], [0.0, 0.0, 0.0, 0.0]])
+    for nu in (1.3, 3.7):
+        assert orc.dissim_scale(X, nu, orc.EXACT)[0, 1] == pytest.approx(
+            orc.dissim(X, [nu], orc.EXACT)[0][0, 1], rel=1e-13)
+
+
+@pytest.mark.parametrize("latent,p,loss", [(0, 2, 0), (0, 3, 0), (1, 2, 0), (1, 3, 0), (0, 2, 1), (1, 3, 1)])
+def test_grad_scale_bounds(orc, latent, p, loss):
+    """B_ic >= |G_ic| for the raw and the Sammon stress; two points (one term)
+    give B == |G| exactly; rows of the full call match the row call."""
+    X, Z = _problem(41 + p, 30, 6, p)
+    D = orc.dissim(X, [2.5], orc.EXACT)[0]
+    S = float(np.triu(D, 1).sum())
+    fn = orc.stress if loss == 0 else orc.sammon
+    _, G = fn(D, Z, 2.5, latent, orc.EXACT)
+    B = orc.grad_scale(D, Z, 2.5, latent, orc.EXACT, loss, S)
+    assert np.all(B >= np.abs(G) * (1 - 1e-12))
+    rows = np.array([0, 11, 29])
+    np.testing.assert_array_equal(orc.grad_scale_rows(D[rows], rows, Z, 2.5, latent, orc.EXACT, loss, S), B[rows])
+    D2 = D[:2, :2].copy()
+    _, G2 = fn(D2, Z[:2], 2.5, latent, orc.EXACT)
+    B2 = orc.grad_scale(D2, Z[:2], 2.5, latent, orc.EXACT, loss, float(D2[0, 1]))
+    np.testing.assert_allclose(B2, np.abs(G2), rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("latent", [0, 1])
+def test_grad_scale_equals_gradient_when_terms_share_a_sign(orc, latent):
+    """Delta = 0 makes every residual r = delta >= 0.  At p = 2, the point with
+    the largest Z_1 - Z_0 sees u_1 > u_0 against every other point, so every
+    Gini term has the sign pattern (-, +); the point with the largest Z_0 has
+    u_0 > 0 against every other point, so every Euclidean term of coordinate 0
+    is positive.  Then B equals |G| there; elsewhere B > |G| somewhere."""
+    g = np.random.Generator(np.random.PCG64(17))
+    n = 40
+    Z = g.standard_normal((n, 2))
+    D = np.zeros((n, n))
+    _, G = orc.stress(D, Z, 1.8, latent, orc.EXACT)
+    B = orc.grad_scale(D, Z, 1.8, latent, orc.EXACT)
+    if latent == 0:
+        i = int(np.argmax(Z[:, 1] - Z[:, 0]))
+        np.testing.assert_allclose(B[i], np.abs(G[i]), rtol=1e-13)
+    else:
+        i = int(np.argmax(Z[:, 0]))
+        assert B[i, 0] == pytest.approx(abs(G[i, 0]), rel=1e-13)
+    assert np.any(B > np.abs(G) * (1 + 1e-6))
+
+
+def test_grad_scale_homogeneity(orc):
+    """Scaling Delta and Z by 2: the raw-stress terms 2 r a scale by 2; the
+    Sammon terms 2 r a / (S Delta) by 1/2."""
+    X, Z = _problem(43, 24, 5, 3)
+    D = orc.dissim(X, [2.0], orc.EXACT)[0]
+    S = float(np.triu(D, 1).sum())
+    B = orc.grad_scale(D, Z, 2.0, 0, orc.EXACT)
+    np.testing.assert_allclose(orc.grad_scale(2 * D, 2 * Z, 2.0, 0, orc.EXACT), 2 * B, rtol=1e-13)
+    Bs = orc.grad_scale(D, Z, 2.0, 0, orc.EXACT, 1, S)
+    np.testing.assert_allclose(orc.grad_scale(2 * D, 2 * Z, 2.0, 0, orc.EXACT, 1, 2 * S), Bs / 2, rtol=1e-13)
