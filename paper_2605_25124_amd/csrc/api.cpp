@@ -402,10 +402,14 @@ int64_t layout(InstDesc& D, int T) {
     return gmds::tri_count(D.nb) * gmds::units_per_tile(T);
 }
 
+// Scratch floats of one instance: row partials, column partials, per-wave
+// stress partials and the stress slices of the reduction (two floats for
+// each of up to kSigSlices slices; assign_partials lays them out in order).
 size_t partial_floats(const InstDesc& D, int T, int pg) {
     const int64_t nt = gmds::tri_count(D.nb);
     const int64_t u = gmds::units_per_tile(T);
-    return (size_t)nt * T * pg + (size_t)nt * u * T * pg + (size_t)nt * u * gmds::kStressWaves * 2 + 32;
+    return (size_t)nt * T * pg + (size_t)nt * u * T * pg + (size_t)nt * u * gmds::kStressWaves * 2 +
+           2 * (size_t)gmds::kSigSlices;
 }
 
 void assign_partials(InstDesc& D, float* base, int T, int pg) {

@@ -9,6 +9,7 @@ namespace gmds {
 constexpr int kMaxP = 8;           // latent dimensions supported by the stress kernels
 constexpr int kMaxNu = 64;         // nu values per gini_dissim call
 constexpr int kStressWaves = 4;    // waves per stress workgroup (one stress partial each)
+constexpr int kSigSlices = 32;     // most stress slices one instance's reduction sums (scratch: 2 floats each)
 constexpr int kMaxCmdsQ = 8;       // widest subspace of the classical-MDS iteration
 constexpr int kLossRaw = 0;        // raw stress sum (delta - Delta)^2
 constexpr int kLossSammon = 1;     // Sammon stress sum (delta - Delta)^2 / Delta over sum Delta
@@ -28,7 +29,7 @@ struct InstDesc {
     float* rowpart;        // scratch: [ntiles][T][pg] row partial gradients (one per row and tile)
     float* colpart;        // scratch: [ntiles][units][T][pg] column partial gradients (one per unit)
     float* sigpart;        // scratch: [ntiles][units][kStressWaves][2] partial stress (hi, lo) per wave
-    float* sigslice;       // scratch: [16][2] stress slices of the reduction launch
+    float* sigslice;       // scratch: [kSigSlices][2] stress slices of the reduction launch
     uint32_t* instcnt;     // [1] finished stress slices / units; zero between launches
     int64_t n, ldd, ldz, ldg;
     int64_t nb;            // tiles per side = ceil(n / T)

@@ -94,6 +94,12 @@ __device__ __forceinline__ float weigh(float r, float d) {
     else return r;
 }
 
+// h with its sign flipped where s is negative (s a coordinate difference):
+// one bit operation.
+__device__ __forceinline__ float signed_as(float h, float s) {
+    return __int_as_float(__float_as_int(h) ^ (__float_as_int(s) & (int)0x80000000u));
+}
+
 template <int P, int LAT, int LOSS, bool GRAD, bool MASK>
 __device__ __forceinline__ void pair_term(const float (&zi)[P], const float (&zj)[P], float d, bool valid,
                                           int p, const InstDesc& D, float (&g)[PG_<P, LAT>::value], float& sst) {
@@ -369,15 +375,24 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
                         }
                     }
             }
-        } else if constexpr (P == 3 && LAT == 0 && !MASK) {
-            // p = 3 Gini on an interior tile.  An untied pair's gradient term is
-            // +h on its largest coordinate, -h on its smallest and 0 on the
-            // middle one (h = weighted residual times a_max), so it sums to
-            // zero over the coordinates: only components 0 and 1 are
-            // accumulated, and component 2 collects the coordinate sums of the
-            // tied pairs (general rule), from which it is recovered per row
-            // and per column as sum - c0 - c1.
+        } else if constexpr (P == 3 && LAT == 0) {
+            // p = 3 Gini.  Untied u takes the doubled midranks (2, 4, 6) in
+            // sorted order and the middle weight is exactly 0, so
+            // delta = a (u_max - u_min) with a = (3/2) W_3[6]; over the
+            // coordinate differences d_ab = u_a - u_b, u_max - u_min is
+            // max |d_ab| (the same rounded difference).  The gradient term is
+            // +h on the largest coordinate, -h on the smallest and 0 on the
+            // middle one (h = a times the weighted residual): with s_ab = h/2
+            // carrying the sign of d_ab, the term of coordinate a is
+            // s_ab + s_ac, and h/2 + h/2 = h, h/2 - h/2 = 0 exactly, so each
+            // accumulated term equals the general rule's and no component is
+            // recovered from the others.  A tied pair (some d_ab == 0) or a
+            // pair outside the triangle gets r = 0 here and adds nothing; if
+            // some lane of the wave holds a tied pair of the triangle, the
+            // step's tied pairs then take the general midrank rule.
             const float wmax = D.wtab[4];
+            const float whalf = 0.5f * wmax;
+            bool tied = false;
 #pragma unroll
             for (int q = 0; q < NQ; ++q)
 #pragma unroll
@@ -385,38 +400,53 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
                     const int x = q * 4 + e;
                     const float d = buf[q][e];
                     const float u0 = zi[0] - zj[x][0], u1 = zi[1] - zj[x][1], u2 = zi[2] - zj[x][2];
-                    const float mx = fmaxf(fmaxf(u0, u1), u2);
-                    const float mn = fminf(fminf(u0, u1), u2);
-                    const float md = __builtin_amdgcn_fmed3f(u0, u1, u2);
-                    float g0 = 0.f, g1 = 0.f;
-                    if (mx != md && mn != md) {
-                        const float r = fmaf(wmax, mx - mn, -d);
-                        const float rw = weigh<LOSS>(r, d);
-                        sst = fmaf(r, rw, sst);
-                        if constexpr (GRAD) {
-                            const float h = rw * wmax;
-                            g0 = (u0 == mx) ? h : ((u0 == mn) ? -h : 0.f);
-                            g1 = (u1 == mx) ? h : ((u1 == mn) ? -h : 0.f);
-                        }
-                    } else {
-                        float g[PG];
-                        pair_term<P, LAT, LOSS, GRAD, MASK>(zi, zj[x], d, true, p, D, g, sst);
-                        if constexpr (GRAD) {
-                            g0 = g[0];
-                            g1 = g[1];
-                            const float sum = (g[0] + g[1]) + g[2];
-                            rowacc[2] += sum;
-                            colacc[x][2] += sum;
-                        }
+                    const float d01 = u0 - u1, d02 = u0 - u2, d12 = u1 - u2;
+                    const float span = fmaxf(fmaxf(fabsf(d01), fabsf(d02)), fabsf(d12));
+                    const float gap = fminf(fminf(fabsf(d01), fabsf(d02)), fabsf(d12));
+                    bool valid = true;
+                    if constexpr (MASK) {
+                        const int jl = 4 * (c4 + q * kLPR) + e;
+                        valid = (il < rows_left) && (jl < cols_left) && (!diag || jl > il);
                     }
+                    const bool tie = gap == 0.f;
+                    tied |= valid && tie;
+                    float r = fmaf(wmax, span, -d);
+                    r = (valid && !tie) ? r : 0.f;
+                    const float rw = weigh<LOSS>(r, d);
+                    sst = fmaf(r, rw, sst);
                     if constexpr (GRAD) {
+                        const float hh = rw * whalf;
+                        const float s01 = signed_as(hh, d01), s02 = signed_as(hh, d02), s12 = signed_as(hh, d12);
+                        const float g0 = s01 + s02, g1 = s12 - s01, g2 = -(s02 + s12);
                         rowacc[0] += g0;
                         rowacc[1] += g1;
+                        rowacc[2] += g2;
                         colacc[x][0] += g0;
                         colacc[x][1] += g1;
+                        colacc[x][2] += g2;
                     }
                 }
-            if constexpr (GRAD) rowacc[PG - 1] = rowacc[PG - 1] - rowacc[0] - rowacc[1];
+            if (__builtin_amdgcn_ballot_w64(tied) != 0) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int x = q * 4 + e;
+                        const int jl = 4 * (c4 + q * kLPR) + e;
+                        const bool valid = !MASK || ((il < rows_left) && (jl < cols_left) && (!diag || jl > il));
+                        const float u0 = zi[0] - zj[x][0], u1 = zi[1] - zj[x][1], u2 = zi[2] - zj[x][2];
+                        const bool tie = (u0 == u1) || (u0 == u2) || (u1 == u2);
+                        float g[PG];
+                        pair_term<P, LAT, LOSS, GRAD, true>(zi, zj[x], buf[q][e], valid && tie, p, D, g, sst);
+                        if constexpr (GRAD) {
+#pragma unroll
+                            for (int c = 0; c < PG; ++c) {
+                                rowacc[c] += g[c];
+                                colacc[x][c] += g[c];
+                            }
+                        }
+                    }
+            }
         } else {
 #pragma unroll
             for (int q = 0; q < NQ; ++q)
@@ -453,10 +483,6 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
     }
 
     if constexpr (GRAD) {
-        if constexpr (P == 3 && LAT == 0 && !MASK) {
-#pragma unroll
-            for (int x = 0; x < CPT; ++x) colacc[x][PG - 1] = colacc[x][PG - 1] - colacc[x][0] - colacc[x][1];
-        }
         // column partials: the 16 row groups hold partial sums of each column
 #pragma unroll
         for (int c = 0; c < PG; ++c) {
@@ -645,8 +671,8 @@ __device__ void reduce_group(const InstDesc& D, int64_t k0, int mode, float* lds
 // Stress of instance D from the per-wave unit partials (units past n, only in
 // the last tile, hold nothing), in contiguous slices.  A slice is a fixed
 // shape sum: virtual thread v < kVT adds partials a+v, a+v+kVT, ... in order,
-// then a fixed binary tree over the kVT values; slices are added in order.
-constexpr int kSigSlices = 32;
+// then a fixed binary tree over the kVT values; slices are added in order
+// (at most kSigSlices of them, the room the host reserves per instance).
 
 template <int T>
 __device__ __forceinline__ int64_t sigma_count(const InstDesc& D) {

@@ -165,13 +165,18 @@ def _dev_index(t: torch.Tensor) -> int:
 
 
 def _mat(t: torch.Tensor, name: str, dtype=torch.float32) -> int:
+    """Leading dimension of a row-major matrix whose rows do not overlap
+    (unit column stride, row stride >= the row length); anything else -- an
+    expanded or transposed view -- is rejected rather than read as dense."""
     if t.dtype != dtype:
         raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
     if t.dim() != 2:
         raise ValueError(f"{name} must be 2-D")
     if t.shape[1] > 1 and t.stride(1) != 1:
         raise ValueError(f"{name} must have unit column stride")
-    return max(int(t.stride(0)), int(t.shape[1])) if t.shape[0] > 1 else int(t.shape[1])
+    if t.shape[0] > 1 and int(t.stride(0)) < int(t.shape[1]):
+        raise ValueError(f"{name} has row stride {t.stride(0)} < row length {t.shape[1]} (overlapping rows)")
+    return int(t.stride(0)) if t.shape[0] > 1 else int(t.shape[1])
 
 
 def _stream(dev: int) -> ctypes.c_void_p:
@@ -230,6 +235,10 @@ def gini_dissim(X: torch.Tensor, nus: Sequence[float], out: Optional[torch.Tenso
         raise ValueError("out must have shape (len(nus), n, n)")
     if out.dtype != torch.float32 or (n > 1 and out.stride(2) != 1):
         raise ValueError("out must be FP32 with unit column stride")
+    if n > 1 and int(out.stride(1)) < n:
+        raise ValueError(f"out has row stride {out.stride(1)} < n = {n} (overlapping rows)")
+    if len(nus) > 1 and int(out.stride(0)) < n * int(out.stride(1)):
+        raise ValueError("the matrices of out overlap")
     ldd = int(out.stride(1)) if n > 1 else 1
     stride_nu = int(out.stride(0))
     c = context(dev)
@@ -248,7 +257,11 @@ def _sum_call(fn, Delta: torch.Tensor, out: Optional[torch.Tensor] = None) -> to
     if D3.dtype != torch.float32 or (D3.shape[1] > 1 and D3.stride(2) != 1):
         raise ValueError("Delta must be FP32 with unit column stride")
     k, n = int(D3.shape[0]), int(D3.shape[1])
-    ldd = max(int(D3.stride(1)), n) if n > 1 else 1
+    if n > 1 and int(D3.stride(1)) < n:
+        raise ValueError(f"Delta has row stride {D3.stride(1)} < n = {n} (overlapping rows)")
+    if k > 1 and int(D3.stride(0)) < n * int(D3.stride(1)):
+        raise ValueError("the matrices of a Delta stack overlap")
+    ldd = int(D3.stride(1)) if n > 1 else 1
     if out is None:
         out = torch.empty((k, 2), dtype=torch.float32, device=Delta.device)
     if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != 2 * k:
@@ -469,7 +482,11 @@ def gini_select_nu(X: torch.Tensor, nus: Sequence[float], Z0: torch.Tensor, iter
         raise ValueError("Z_out must be an FP32 tensor of shape (len(nus), n, p)")
     if p > 1 and Z_out.stride(2) != 1:
         raise ValueError("Z_out must have unit column stride")
-    ldzo = max(int(Z_out.stride(1)), p) if n > 1 else p
+    if n > 1 and int(Z_out.stride(1)) < p:
+        raise ValueError("Z_out has overlapping rows")
+    if k > 1 and int(Z_out.stride(0)) < n * int(Z_out.stride(1)):
+        raise ValueError("the configurations of Z_out overlap")
+    ldzo = int(Z_out.stride(1)) if n > 1 else p
     nus_h = (ctypes.c_double * k)(*[float(v) for v in nus])
     ks_mean = np.zeros(k, dtype=np.float64)
     ks_fold = np.zeros((k, int(folds)), dtype=np.float64)

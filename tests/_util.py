@@ -32,3 +32,34 @@ def rel(a, b):
     b = np.asarray(b, dtype=np.float64)
     nb = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def assert_grad_close(G_gpu, G_ref, B, rtol=1e-4, extra=0.0, what=""):
+    """Gradient parity entry by entry: |G_gpu - G_ref| <= rtol * B + extra, with
+    B the oracle's sum of the absolute values of the terms whose sum is each
+    entry (oracle.grad_scale / grad_scale_rows), and the relative 2-norm within
+    rtol as well.  `extra` covers rounding that is not the gradient's (a step
+    recovered from two iterates).  Returns the worst |error| / B."""
+    G_gpu = np.asarray(G_gpu, dtype=np.float64)
+    G_ref = np.asarray(G_ref, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    err = np.abs(G_gpu - G_ref)
+    bound = rtol * B + extra + 1e-30
+    bad = err > bound
+    if bad.any():
+        k = int(np.argmax(err / bound))
+        raise AssertionError(f"{what}: {int(bad.sum())} gradient entries off; worst at {np.unravel_index(k, err.shape)}: "
+                             f"err {err.flat[k]:.3e} vs bound {bound.flat[k]:.3e} (ref {G_ref.flat[k]:.6e}, "
+                             f"scale {B.flat[k]:.3e})")
+    r = rel(G_gpu, G_ref)
+    assert r <= rtol, (what, r)
+    return float(np.max(err / (B + 1e-300))) if err.size else 0.0
+
+
+def step_rounding(Z0, Z1, eta, G_ref):
+    """What rounding adds to a gradient recovered as (Z0 - Z1) / eta from one
+    FP32 descent step Z1 = fl32(Z0 - eta32 G): half an ulp of Z1 over eta, and
+    the roundings of eta to FP32 and of eta32 G (each relative 2^-24 of G)."""
+    Z0 = np.abs(np.asarray(Z0, dtype=np.float64))
+    Z1 = np.abs(np.asarray(Z1, dtype=np.float64))
+    return 2.0 ** -24 * (np.maximum(Z0, Z1) / eta + 2.0 * np.abs(np.asarray(G_ref, dtype=np.float64))) * 1.01

@@ -316,3 +316,16 @@ def test_binding_refuses_cpu_tensors(gm):
         gm.gini_rank(torch.zeros(3, 4))
     with pytest.raises(ValueError):
         gm.gini_dissim(torch.zeros(3, 4), [2.0])
+
+
+def test_binding_rejects_overlapping_rows(gm):
+    """An expanded or transposed view is not a row-major matrix with rows of
+    their own: the binding refuses it instead of reading it as dense."""
+    import torch
+    with pytest.raises(ValueError):
+        gm._mat(torch.zeros(1, 3).expand(5, 3), "Z")
+    with pytest.raises(ValueError):
+        gm._mat(torch.zeros(4, 3).t(), "Z")
+    assert gm._mat(torch.zeros(5, 3), "Z") == 3
+    assert gm._mat(torch.zeros(5, 8)[:, :3], "Z") == 8
+    assert gm._mat(torch.zeros(1, 3), "Z") == 3

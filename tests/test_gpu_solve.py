@@ -5,7 +5,7 @@ import pytest
 import torch
 
 from paper_2605_25124_amd import synth
-from tests._util import rel
+from tests._util import assert_grad_close, step_rounding
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
@@ -75,9 +75,11 @@ def test_teacher_forced_steps(gm, orc, latent, p):
         h = torch.zeros(1, device=DEV)
         gm.gini_mds_solve([gm.Instance(D, Z, nu, latent, 0.0, h)], 1, gm.SOLVE_PERSISTENT)
         s_ref, G_ref = orc.stress(Dn, Zt, nu, latent, orc.MATCH32)
+        B = orc.grad_scale(Dn, Zt, nu, latent, orc.MATCH32)
         assert abs(float(h[0]) - s_ref) <= 1e-4 * s_ref, t
-        step = (Zt.astype(np.float64) - Z.cpu().numpy().astype(np.float64)) / eta
-        assert rel(step, G_ref) <= 1e-4, (t, rel(step, G_ref))
+        Z0n, Z1n = Zt.astype(np.float64), Z.cpu().numpy().astype(np.float64)
+        step = (Z0n - Z1n) / eta
+        assert_grad_close(step, G_ref, B, 1e-4, step_rounding(Z0n, Z1n, eta, G_ref), f"step {t}")
 
 
 def test_small_workload_descends_like_oracle(gm, orc):
