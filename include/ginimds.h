@@ -36,6 +36,7 @@
 #ifndef GINIMDS_H
 #define GINIMDS_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -180,6 +181,29 @@ gini_status gini_stress_bwd(gini_ctx* ctx, const float* Delta, int64_t n, int64_
                             const float* Z, int32_t p, int64_t ldz, double nu, gini_latent latent,
                             const float* grad_out, float* gradZ, int64_t ldg, float* out_sigma,
                             gini_stream_t stream);
+
+/*
+ * gini_stress_bwd_static -- gini_stress_bwd for callers that cannot allocate
+ * device memory: work recorded under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, kernels and bitwise
+ * results as gini_stress_bwd, but the call allocates nothing (no hipMalloc,
+ * hipFree or allocating library call): the tile partials, the descriptor and
+ * the stress-slice counter live in one static device array of
+ * GINI_STATIC_SCRATCH_BYTES that every GPU the library runs on holds until
+ * the process ends; its address is looked up at the first call on a device.
+ * That bounds the size: at p = 2 with the Gini latent n up to about 36 000,
+ * at p = 3 (or p = 2 Euclidean: two stored gradient components) about 21 000
+ * (26 000); a larger problem returns GINI_EUNSUPPORTED with the bytes it
+ * needs, before anything is launched.  Every call on one GPU shares that GPU's
+ * array, and each call clears what must start at zero: calls that overlap
+ * on one GPU (other streams, other host threads) race on it and must be
+ * serialised by the caller.  Profiling (gini_profile_enable) does not time it.
+ */
+#define GINI_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+gini_status gini_stress_bwd_static(gini_ctx* ctx, const float* Delta, int64_t n, int64_t ldd,
+                                   const float* Z, int32_t p, int64_t ldz, double nu, gini_latent latent,
+                                   const float* grad_out, float* gradZ, int64_t ldg, float* out_sigma,
+                                   gini_stream_t stream);
 
 /*
  * gini_sammon_fwd / gini_sammon_bwd -- as gini_stress_fwd / gini_stress_bwd

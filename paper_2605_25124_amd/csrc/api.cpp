@@ -13,6 +13,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -29,6 +30,7 @@ constexpr int kVersion = 10000;     // 1.0.0
 constexpr int kRing = 16;           // descriptor upload slots
 constexpr int64_t kMaxRankD = 1 << 20;
 constexpr int kMaxDissimM = 4096;
+constexpr int kErrCap = 512;        // longest error message, with its terminator
 
 struct Slot {
     void* host = nullptr;   // pinned
@@ -86,7 +88,7 @@ struct gini_ctx {
 namespace {
 
 gini_status fail(gini_ctx* c, gini_status s, const char* fmt, ...) {
-    char buf[512];
+    char buf[kErrCap];
     va_list ap;
     va_start(ap, fmt);
     vsnprintf(buf, sizeof buf, fmt, ap);
@@ -320,11 +322,10 @@ gini_status ensure_counters(gini_ctx* c, size_t words, hipStream_t s) {
 // the weight a coordinate of doubled midrank t receives in the symmetrised
 // generalised Gini pseudo-distance.  Built in FP64 as A[t] - A[2d+2-t] so that
 // the FP32 table is exactly antisymmetric, W[2d+2-t] == -W[t].
+double weight_part(int d, double nu, int t) { return std::pow((double)(t - 2) / (2.0 * d), nu - 1.0); }
+
 void weight_table(int d, double nu, double* out) {
-    const int len = 2 * d - 1;
-    std::vector<double> A(len);
-    for (int t = 2; t <= 2 * d; ++t) A[t - 2] = std::pow((double)(t - 2) / (2.0 * d), nu - 1.0);
-    for (int t = 2; t <= 2 * d; ++t) out[t - 2] = A[t - 2] - A[2 * d - t];
+    for (int t = 2; t <= 2 * d; ++t) out[t - 2] = weight_part(d, nu, t) - weight_part(d, nu, 2 * d + 2 - t);
 }
 
 gini_status get_tables(gini_ctx* c, int d, const double* nu, int n_nu, hipStream_t s, float** dev) {
@@ -370,8 +371,8 @@ void latent_consts(int p, double nu, int latent, InstDesc& D, double& c) {
     D.c2 = 0.f;
     c = 1.0;
     if (latent == GINI_LATENT_GINI) {
-        std::vector<double> w(2 * p - 1);
-        weight_table(p, nu, w.data());
+        double w[2 * gmds::kMaxP - 1];
+        weight_table(p, nu, w);
         for (int i = 0; i < 2 * p - 1; ++i) D.wtab[i] = (float)(0.5 * p * w[i]);
         if (p == 2) D.c2 = D.wtab[2];
         c = 0.0;
@@ -421,11 +422,10 @@ void assign_partials(InstDesc& D, float* base, int T, int pg) {
     D.sigslice = D.sigpart + (size_t)nt * u * gmds::kStressWaves * 2;
 }
 
-gini_status stress_common(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, const float* Z, int32_t p,
-                          int64_t ldz, double nu, gini_latent latent, const float* grad_out, float* gradZ,
-                          int64_t ldg, float* out_sigma, bool grad, int loss, const float* dsum, hipStream_t s) {
-    if (!c) return GINI_EINVAL;
-    c->err.clear();
+// Argument checks of one stress evaluation (host only, no HIP call).
+gini_status check_stress_args(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, const float* Z, int32_t p,
+                              int64_t ldz, double nu, gini_latent latent, float* gradZ, int64_t ldg,
+                              float* out_sigma, bool grad, int loss, const float* dsum) {
     if (loss == GINI_LOSS_SAMMON && !dsum) return fail(c, GINI_EINVAL, "delta_sum must be non-null");
     if (!Delta || !Z) return fail(c, GINI_EINVAL, "Delta and Z must be non-null");
     if (n < 2) return fail(c, GINI_EINVAL, "n = %lld: need at least two points", (long long)n);
@@ -440,10 +440,15 @@ gini_status stress_common(gini_ctx* c, const float* Delta, int64_t n, int64_t ld
         return fail(c, GINI_EINVAL, "out_sigma must be non-null");
     }
     if ((uint64_t)n > (uint64_t)1 << 31) return fail(c, GINI_EUNSUPPORTED, "n > 2^31 is not supported");
-    st = ensure_ready(c);
-    if (st != GINI_OK) return st;
-    const int T = pick_tile(n);
-    InstDesc D{};
+    return GINI_OK;
+}
+
+// Descriptor of one stress evaluation at tile T (everything but the scratch
+// pointers); returns its number of work units.
+int64_t stress_desc(InstDesc& D, const float* Delta, int64_t n, int64_t ldd, const float* Z, int32_t p,
+                    int64_t ldz, double nu, gini_latent latent, const float* grad_out, float* gradZ, int64_t ldg,
+                    float* out_sigma, int loss, const float* dsum, int T) {
+    D = InstDesc{};
     D.Delta = Delta;
     D.Z = const_cast<float*>(Z);
     D.gradZ = gradZ;
@@ -458,7 +463,25 @@ gini_status stress_common(gini_ctx* c, const float* Delta, int64_t n, int64_t ld
     D.p = p;
     double cc;
     latent_consts(p, nu, latent, D, cc);
-    const int64_t nt = layout(D, T);
+    D.tile_off = 0;
+    D.red_off = 0;
+    return layout(D, T);
+}
+
+gini_status stress_common(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, const float* Z, int32_t p,
+                          int64_t ldz, double nu, gini_latent latent, const float* grad_out, float* gradZ,
+                          int64_t ldg, float* out_sigma, bool grad, int loss, const float* dsum, hipStream_t s) {
+    if (!c) return GINI_EINVAL;
+    c->err.clear();
+    gini_status st = check_stress_args(c, Delta, n, ldd, Z, p, ldz, nu, latent, gradZ, ldg, out_sigma, grad, loss,
+                                       dsum);
+    if (st != GINI_OK) return st;
+    st = ensure_ready(c);
+    if (st != GINI_OK) return st;
+    const int T = pick_tile(n);
+    InstDesc D;
+    const int64_t nt = stress_desc(D, Delta, n, ldd, Z, p, ldz, nu, latent, grad_out, gradZ, ldg, out_sigma, loss,
+                                   dsum, T);
     if (nt > (int64_t)0x7fffffff) return fail(c, GINI_EUNSUPPORTED, "too many tiles");
     const int pg = gmds::stored_components(p, latent);
     st = ensure_scratch(c, partial_floats(D, T, pg) * sizeof(float));
@@ -467,8 +490,6 @@ gini_status stress_common(gini_ctx* c, const float* Delta, int64_t n, int64_t ld
     st = ensure_counters(c, 1, s);
     if (st != GINI_OK) return st;
     D.instcnt = c->cnt;
-    D.tile_off = 0;
-    D.red_off = 0;
     const int64_t rblocks = gmds::reduce_block_count(D.n, D.nb, T);
     void* dd = nullptr;
     Slot* sl = nullptr;
@@ -824,6 +845,50 @@ gini_status check_opts(gini_ctx* c, const gini_solve_opts* o) {
     return GINI_OK;
 }
 
+// ------------------------------------------------------- no-allocation path
+// gini_stress_bwd_static takes its scratch from one static device array per
+// GPU: [0, 256) the descriptor, [256, 512) the stress-slice counter, then the
+// tile partials of gini_stress_bwd's layout.  The array's address is looked
+// up once per device (hipGetSymbolAddress, with that device current) and only
+// that address is handed to kernels.
+constexpr size_t kStaticScratchBytes = GINI_STATIC_SCRATCH_BYTES;
+constexpr size_t kStaticCounter = 256;
+constexpr size_t kStaticHead = 512;
+constexpr int kMaxStaticDevices = 64;
+static_assert(sizeof(InstDesc) <= kStaticCounter, "the descriptor must fit its slot");
+
+std::once_flag g_static_once[kMaxStaticDevices];
+unsigned char* g_static_ptr[kMaxStaticDevices];
+hipError_t g_static_status[kMaxStaticDevices];
+
+// Writes the descriptor (a kernel argument) into its slot and clears the
+// counter, so nothing the array kept from an earlier call is read.
+__global__ void k_put_desc(InstDesc D, InstDesc* dst, uint32_t* cnt) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *dst = D;
+        *cnt = 0u;
+    }
+}
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+gini_status static_scratch(gini_ctx* c, unsigned char** base) {
+    const int dev = c->device;
+    if (dev >= kMaxStaticDevices) return fail(c, GINI_EUNSUPPORTED, "device %d: static scratch for devices < %d only",
+                                              dev, kMaxStaticDevices);
+    GINI_HIP(c, hipSetDevice(dev));
+    std::call_once(g_static_once[dev], [dev] {
+        g_static_status[dev] = hipGetSymbolAddress(reinterpret_cast<void**>(&g_static_ptr[dev]), HIP_SYMBOL(scratch));
+    });
+    if (g_static_status[dev] != hipSuccess) return hip_fail(c, g_static_status[dev], "hipGetSymbolAddress(scratch)");
+    *base = g_static_ptr[dev];
+    return GINI_OK;
+}
+
 }  // namespace
 
 // ======================================================================= C ABI
@@ -836,6 +901,7 @@ gini_status gini_create(gini_ctx** ctx, int device) {
     gini_ctx* c = new (std::nothrow) gini_ctx();
     if (!c) return GINI_ENOMEM;
     c->device = device;
+    c->err.reserve(kErrCap);   // fail() then never reallocates the message
     if (const char* v = std::getenv("GINI_SPIN_LIMIT_TICKS")) {
         const long long t = std::atoll(v);
         if (t > 0) {
@@ -1020,6 +1086,40 @@ gini_status gini_stress_bwd(gini_ctx* c, const float* Delta, int64_t n, int64_t 
                             int64_t ldg, float* out_sigma, gini_stream_t stream) {
     return stress_common(c, Delta, n, ldd, Z, p, ldz, nu, latent, grad_out, gradZ, ldg, out_sigma, true,
                          GINI_LOSS_RAW, nullptr, reinterpret_cast<hipStream_t>(stream));
+}
+
+gini_status gini_stress_bwd_static(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, const float* Z,
+                                   int32_t p, int64_t ldz, double nu, gini_latent latent, const float* grad_out,
+                                   float* gradZ, int64_t ldg, float* out_sigma, gini_stream_t stream) {
+    if (!c) return GINI_EINVAL;
+    c->err.clear();
+    gini_status st = check_stress_args(c, Delta, n, ldd, Z, p, ldz, nu, latent, gradZ, ldg, out_sigma, true,
+                                       GINI_LOSS_RAW, nullptr);
+    if (st != GINI_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int T = pick_tile(n);
+    InstDesc D;
+    const int64_t nt = stress_desc(D, Delta, n, ldd, Z, p, ldz, nu, latent, grad_out, gradZ, ldg, out_sigma,
+                                   GINI_LOSS_RAW, nullptr, T);
+    const int pg = gmds::stored_components(p, latent);
+    const size_t need = kStaticHead + partial_floats(D, T, pg) * sizeof(float);
+    if (nt > (int64_t)0x7fffffff || need > kStaticScratchBytes)
+        return fail(c, GINI_EUNSUPPORTED,
+                    "n = %lld, p = %d needs %zu bytes of scratch; the static array holds %zu "
+                    "(gini_stress_bwd has no such limit)",
+                    (long long)n, p, need, kStaticScratchBytes);
+    unsigned char* base = nullptr;
+    st = static_scratch(c, &base);
+    if (st != GINI_OK) return st;
+    assign_partials(D, reinterpret_cast<float*>(base + kStaticHead), T, pg);
+    D.instcnt = reinterpret_cast<uint32_t*>(base + kStaticCounter);
+    InstDesc* dd = reinterpret_cast<InstDesc*>(base);
+    hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, D, dd, D.instcnt);
+    GINI_HIP(c, hipGetLastError());
+    GINI_HIP(c, gmds::launch_stress_units(dd, 1, nt, 0, p, latent, T, true, GINI_LOSS_RAW, s));
+    GINI_HIP(c, gmds::launch_stress_reduce(dd, 1, gmds::reduce_block_count(D.n, D.nb, T), 0, p, latent, T,
+                                           gmds::kModeGrad, 0, s));
+    return GINI_OK;
 }
 
 gini_status gini_sammon_fwd(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, const float* delta_sum,

@@ -96,6 +96,7 @@ def _load():
     L.gini_sammon_step.argtypes = [P, P, i64, i64, i32, f64, ctypes.c_int, ctypes.POINTER(f64), P]
     L.gini_stress_fwd.argtypes = [P, P, i64, i64, P, i32, i64, f64, ctypes.c_int, P, P]
     L.gini_stress_bwd.argtypes = [P, P, i64, i64, P, i32, i64, f64, ctypes.c_int, P, P, i64, P, P]
+    L.gini_stress_bwd_static.argtypes = [P, P, i64, i64, P, i32, i64, f64, ctypes.c_int, P, P, i64, P, P]
     L.gini_mds_solve.argtypes = [P, ctypes.POINTER(_Instance), i32, ctypes.POINTER(_Opts), P]
     L.gini_autotune.argtypes = [P, ctypes.POINTER(_Instance), i32, i32, ctypes.POINTER(_Opts), P]
     L.gini_select_nu.argtypes = [P, P, i64, i32, i64, P, i32, P, i64, ctypes.POINTER(_SelectOpts), P, i64, i64,
@@ -107,7 +108,7 @@ def _load():
     L.gini_profile_enable.argtypes = [P, ctypes.c_int]
     L.gini_profile_read.argtypes = [P, ctypes.POINTER(_Profile)]
     for fn in ("gini_create", "gini_rank", "gini_dissim", "gini_sumsq", "gini_sum", "gini_sammon_fwd",
-               "gini_sammon_bwd", "gini_sammon_step", "gini_stress_fwd", "gini_stress_bwd",
+               "gini_sammon_bwd", "gini_sammon_step", "gini_stress_fwd", "gini_stress_bwd", "gini_stress_bwd_static",
                "gini_mds_solve", "gini_autotune", "gini_select_nu", "gini_alternate_nu", "gini_classical_mds",
                "gini_standardize", "gini_profile_enable",
                "gini_profile_read"):
@@ -324,6 +325,30 @@ def gini_stress_bwd(Delta: torch.Tensor, Z: torch.Tensor, nu: float, latent: int
     c = context(dev)
     c.check(_lib.gini_stress_bwd(c.handle, _ptr(Delta), n, ldd, _ptr(Z), p, ldz, float(nu), int(latent),
                                  _ptr(grad_out), _ptr(gradZ), ldg, _ptr(out_sigma), _stream(dev)))
+    return gradZ, out_sigma
+
+
+def gini_stress_bwd_static(Delta: torch.Tensor, Z: torch.Tensor, nu: float, latent: int = LATENT_GINI,
+                           grad_out: Optional[torch.Tensor] = None, gradZ: Optional[torch.Tensor] = None,
+                           out_sigma: Optional[torch.Tensor] = None):
+    """gini_stress_bwd through the entry point that allocates no device memory
+    (its scratch is a static device array per GPU): (gradZ, sigma pair).  With
+    gradZ and out_sigma passed in, nothing is allocated on this call at all."""
+    dev = _dev_index(Delta)
+    _check_pair(Delta, Z)
+    ldd = _mat(Delta, "Delta")
+    ldz = _mat(Z, "Z")
+    n, p = Z.shape
+    if gradZ is None:
+        gradZ = torch.empty((n, p), dtype=torch.float32, device=Delta.device)
+    ldg = _mat(gradZ, "gradZ")
+    if out_sigma is None:
+        out_sigma = torch.empty(2, dtype=torch.float32, device=Delta.device)
+    if grad_out is not None and (grad_out.dtype != torch.float32 or grad_out.numel() != 1):
+        raise ValueError("grad_out must be a one-element FP32 tensor")
+    c = context(dev)
+    c.check(_lib.gini_stress_bwd_static(c.handle, _ptr(Delta), n, ldd, _ptr(Z), p, ldz, float(nu), int(latent),
+                                        _ptr(grad_out), _ptr(gradZ), ldg, _ptr(out_sigma), _stream(dev)))
     return gradZ, out_sigma
 
 
