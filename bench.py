@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--workload", choices=["images", "heavy"], default="images",
                     help="images: n = 10^4 image rows, p = 2 (the default); heavy: n = 5*10^4 Student-t rows, "
                          "m = 64, p = 3 (one line for this workload only)")
+    ap.add_argument("--p", type=int, default=0,
+                    help="latent dimensions of the heavy workload (default 3; 2 measures the pure-HBM p = 2 case)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the Sammon-loss and classical-MDS measurements on the image workload")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -93,6 +95,106 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def host_cpu():
+    """nproc and the CPU model name of the host the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
+def cpu_leg(args, w, D, Z0, nu, p, gm, dev):
+    """The oracle timed on a bounded sample of the workload, one thread pinned
+    to one core: its dissimilarity build on the first `ns` rows (the real Gini
+    Delta of the sample), then descent steps on that Delta for about
+    --cpu-seconds; both extrapolated to the full n by n^2 (labelled as such).
+    Then the GPU's results against the oracle on the same inputs: ranks
+    (count of mismatches), Delta (error over the condition scale on sampled
+    pairs, and the plain relative error), the stress and the gradient (per
+    entry over the term-magnitude sums) on a subsample of points."""
+    import numpy as np
+    import torch
+    from oracle import oracle as O
+
+    n, m = w.X.shape
+    ns = 400 if m > 128 else 700
+    old_aff = os.sched_getaffinity(0)
+    core = min(old_aff)
+    os.sched_setaffinity(0, {core})
+    try:
+        Xs = w.X[:ns]
+        t0 = time.perf_counter()
+        Dso = O.dissim(Xs, [nu], O.MATCH32)[0]
+        t_delta = time.perf_counter() - t0
+        Zs = w.Z0[0][:ns, :p].astype(np.float64)
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            Zs, _ = O.solve(Dso, Zs, nu, 1, O.LATENT_GINI, O.MATCH32)   # stress + gradient + step
+            reps += 1
+            if time.perf_counter() - t0 >= args.cpu_seconds:
+                break
+        t_steps = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, old_aff)
+    sp = ns * (ns - 1) // 2
+    full = n * (n - 1) // 2
+    step_rate = reps * sp / t_steps
+    cpu = {"value": round(step_rate, 1), "unit": "pair-evals/s", "cores": 1, "kind": "oracle",
+           "sample": f"FP64 oracle, one thread pinned to one core: Gini Delta of the first {ns} rows of the "
+                     f"workload ({sp} pairs, m={m}) in {t_delta:.2f} s, then {reps} descent steps on it (stress + "
+                     f"gradient + update, p={p} Gini latent) in {t_steps:.1f} s",
+           "dissim_pairs_per_s": round(sp / t_delta, 1),
+           "extrapolated_n2": {"note": f"n^2 extrapolation from the {ns}-row sample to n={n}, not measured",
+                               "dissim_build_s": round(t_delta * full / sp, 1),
+                               "descent_step_s": round(full / step_rate, 3)},
+           "host": host_cpu()}
+
+    # ---- errors of the GPU results against the oracle, on the same inputs
+    g = np.random.Generator(np.random.PCG64(4242))
+    err = {}
+    # ranks: rows of pair differences fl32(x_i - x_j), the vectors ranked inside Delta
+    pi, pj = g.integers(0, n, 256), g.integers(0, n, 256)
+    V = (w.X[pi] - w.X[pj]).astype(np.float32)
+    tr = gm.gini_rank(torch.from_numpy(V).to(dev)).cpu().numpy()
+    err["ranks"] = {"rows": int(V.shape[0]), "d": int(m), "mismatches": int((tr != O.rank2_rows(V)).sum())}
+    # Delta on sampled pairs of the full matrix
+    pi, pj = g.integers(0, n, 2000), g.integers(0, n, 2000)
+    keep = pi != pj
+    pi, pj = pi[keep], pj[keep]
+    got = D[torch.from_numpy(pi).to(dev), torch.from_numpy(pj).to(dev)].cpu().numpy().astype(np.float64)
+    ref = O.dissim_pairs(w.X, pi, pj, [nu], O.MATCH32)[:, 0]
+    S = np.empty(len(pi))
+    for q in range(len(pi)):
+        z = (w.X[pi[q]].astype(np.float32) - w.X[pj[q]].astype(np.float32)).astype(np.float64)
+        _, a = O.gini_dist_grad(z, nu)
+        S[q] = float(np.sum(np.abs(z * a)))
+    big = np.abs(ref) >= 1e-3 * np.abs(ref).max()
+    err["delta"] = {"pairs": int(len(pi)), "max_err_over_scale": float(np.max(np.abs(got - ref) / S)),
+                    "max_rel_err": float(np.max(np.abs(got - ref)[big] / np.abs(ref)[big])), "tolerance": 1e-5}
+    # stress and gradient on a 2000-point subsample (the GPU's Delta entries as the input of both)
+    k = min(n, 2000)
+    idx = np.sort(g.choice(n, k, replace=False))
+    ti = torch.from_numpy(idx).to(dev)
+    Dk = D.index_select(0, ti).index_select(1, ti).contiguous()
+    Zk = Z0.index_select(0, ti).contiguous()
+    G, sig = gm.gini_stress_bwd(Dk, Zk, nu, gm.LATENT_GINI)
+    Dh, Zh = Dk.cpu().numpy().astype(np.float64), Zk.cpu().numpy()
+    s_ref, G_ref = O.stress(Dh, Zh, nu, O.LATENT_GINI, O.MATCH32)
+    B = O.grad_scale(Dh, Zh, nu, O.LATENT_GINI, O.MATCH32)
+    Gn = G.cpu().numpy().astype(np.float64)
+    s_gpu = float(sig[0].double() + sig[1].double())
+    err["sigma"] = {"points": k, "rel_err": abs(s_gpu - s_ref) / abs(s_ref), "tolerance": 1e-4}
+    err["grad"] = {"points": k, "max_err_over_scale": float(np.max(np.abs(Gn - G_ref) / (B + 1e-300))),
+                   "rel_2norm": float(np.linalg.norm(Gn - G_ref) / np.linalg.norm(G_ref)), "tolerance": 1e-4}
+    return cpu, err
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -118,13 +220,17 @@ def main():
     dev = torch.device("cuda:0")
     heavy = args.workload == "heavy"
     if heavy:                                            # its own workload only
-        args.no_sweep = args.no_select = args.no_extras = args.no_cpu_baseline = True
+        args.no_sweep = args.no_select = args.no_extras = True
     w = synth.workload_heavy() if heavy else synth.workload_images(args.n)
     n = w.X.shape[0]
     m = w.X.shape[1]
     pairs = n * (n - 1) // 2
     X = torch.from_numpy(w.X).to(dev)
     Z0 = torch.from_numpy(w.Z0[0]).to(dev)
+    if heavy and args.p:
+        if not 2 <= args.p <= w.Z0[0].shape[1]:
+            raise SystemExit(f"--p must be 2..{w.Z0[0].shape[1]} for the heavy workload")
+        Z0 = Z0[:, :args.p].contiguous()
     p = Z0.shape[1]
     nu = 2.0
     torch.cuda.synchronize()
@@ -236,6 +342,14 @@ def main():
         log(f"sammon {t_sam * 1e6:.1f} us/step (units {sam_us:.1f} us); classical MDS {t_cm * 1e3:.1f} ms, "
             f"{cm_iters} iterations")
 
+    # ---- CPU baseline and errors against the oracle (needs D; run before the
+    # sweep frees it)
+    cpu = None
+    errors = None
+    if not args.no_cpu_baseline:
+        cpu, errors = cpu_leg(args, w, D, Z0, nu, p, gm, dev)
+        log(f"cpu oracle {cpu['value']:.3e} pair-evals/s; errors {json.dumps(errors)}")
+
     # ---- nu-sweep: batched persistent vs plain
     sweep = None
     if not args.no_sweep:
@@ -307,29 +421,6 @@ def main():
                   "ks_mean": [round(float(v), 6) for v in ks_mean]}
         log(f"select: nu* = {wg.nus[bi]} in {ts * 1e3:.1f} ms, KS {select['ks_mean']}")
 
-    # ---- CPU baseline: the oracle as it stands, bounded sample
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle import oracle as O
-        from scipy.spatial.distance import pdist, squareform
-        ns = 3000
-        # stand-in dissimilarities for the sample (their values do not change
-        # the oracle's cost): scaled L1 distances of the same rows
-        Ds_ = squareform(pdist(w.X[:ns].astype(np.float64), "cityblock")) / 784.0
-        Zs = w.Z0[0][:ns].astype(np.float64)
-        reps, t0 = 0, time.perf_counter()
-        while True:
-            Zs, _ = O.solve(Ds_, Zs, nu, 1, O.LATENT_GINI, O.MATCH32)   # stress + gradient + step
-            reps += 1
-            if time.perf_counter() - t0 >= args.cpu_seconds:
-                break
-        el_c = time.perf_counter() - t0
-        cpu = {"value": round(reps * ns * (ns - 1) / 2 / el_c, 1), "unit": "pair-evals/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"oracle descent step (stress + gradient + update, FP64, one thread) on the first "
-                         f"{ns} points of the image workload (p=2 Gini latent), {reps} steps in {el_c:.1f} s"}
-        log(f"cpu oracle {cpu['value']:.3e} pair-evals/s")
-
     out = {"metric": METRIC, "value": round(value, 1), "unit": "pair-evals/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -342,7 +433,8 @@ def main():
                       "parallelism": "single GPU"},
            "hbm_gbs_algorithmic": round(achieved, 1),
            "dissim_build_s": round(dissim_s, 4),
-           "roofline": roof, "sweep": sweep, "select": select, "extras": extras, "cpu_baseline": cpu}
+           "roofline": roof, "sweep": sweep, "select": select, "extras": extras, "cpu_baseline": cpu,
+           "errors": errors}
     print(json.dumps(out), flush=True)
 
 

@@ -191,10 +191,10 @@ gini_status gini_stress_bwd(gini_ctx* ctx, const float* Delta, int64_t n, int64_
  * the stress-slice counter live in one static device array of
  * GINI_STATIC_SCRATCH_BYTES that every GPU the library runs on holds until
  * the process ends; its address is looked up at the first call on a device.
- * That bounds the size: at p = 2 with the Gini latent n up to about 36 000,
- * at p = 3 (or p = 2 Euclidean: two stored gradient components) about 21 000
- * (26 000); a larger problem returns GINI_EUNSUPPORTED with the bytes it
- * needs, before anything is launched.  Every call on one GPU shares that GPU's
+ * That bounds the size: n up to about 36 000 at p = 2 with the Gini latent
+ * (one stored gradient component), 26 000 at p = 3 or at p = 2 with the
+ * Euclidean latent; a larger problem returns GINI_EUNSUPPORTED with the bytes
+ * it needs, before anything is launched.  Every call on one GPU shares that GPU's
  * array, and each call clears what must start at zero: calls that overlap
  * on one GPU (other streams, other host threads) race on it and must be
  * serialised by the caller.  Profiling (gini_profile_enable) does not time it.

@@ -400,7 +400,7 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 int64_t layout(InstDesc& D, int T) {
     D.nb = cdiv(D.n, T);
     D.vec = (aligned16(D.Delta) && (D.ldd % 4) == 0) ? 1 : 0;
-    return gmds::tri_count(D.nb) * gmds::units_per_tile(T);
+    return gmds::tri_count(D.nb) * gmds::units_per_tile(T, D.p);
 }
 
 // Scratch floats of one instance: row partials, column partials, per-wave
@@ -408,14 +408,14 @@ int64_t layout(InstDesc& D, int T) {
 // each of up to kSigSlices slices; assign_partials lays them out in order).
 size_t partial_floats(const InstDesc& D, int T, int pg) {
     const int64_t nt = gmds::tri_count(D.nb);
-    const int64_t u = gmds::units_per_tile(T);
+    const int64_t u = gmds::units_per_tile(T, D.p);
     return (size_t)nt * T * pg + (size_t)nt * u * T * pg + (size_t)nt * u * gmds::kStressWaves * 2 +
            2 * (size_t)gmds::kSigSlices;
 }
 
 void assign_partials(InstDesc& D, float* base, int T, int pg) {
     const int64_t nt = gmds::tri_count(D.nb);
-    const int64_t u = gmds::units_per_tile(T);
+    const int64_t u = gmds::units_per_tile(T, D.p);
     D.rowpart = base;
     D.colpart = base + (size_t)nt * T * pg;
     D.sigpart = D.colpart + (size_t)nt * u * T * pg;
@@ -490,7 +490,7 @@ gini_status stress_common(gini_ctx* c, const float* Delta, int64_t n, int64_t ld
     st = ensure_counters(c, 1, s);
     if (st != GINI_OK) return st;
     D.instcnt = c->cnt;
-    const int64_t rblocks = gmds::reduce_block_count(D.n, D.nb, T);
+    const int64_t rblocks = gmds::reduce_block_count(D.n, D.nb, T, D.p);
     void* dd = nullptr;
     Slot* sl = nullptr;
     st = upload(c, &D, sizeof D, s, &dd, &sl);
@@ -591,7 +591,7 @@ gini_status make_plan(gini_ctx* c, const gini_instance* inst, int32_t n_inst, in
         D.tile_off = P.prefix[k];
         P.prefix[k + 1] = P.prefix[k] + nt;
         D.red_off = P.rblocks;
-        P.rblocks += gmds::reduce_block_count(D.n, D.nb, T);
+        P.rblocks += gmds::reduce_block_count(D.n, D.nb, T, D.p);
         floats += partial_floats(D, T, pg);
         floats = (floats + 63) & ~size_t(63);
     }
@@ -652,7 +652,7 @@ gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStr
                 }
                 ProfScope ps(c, kProfReduce, s, true);
                 GINI_HIP(c, gmds::launch_stress_reduce(ddp + k, 1,
-                                                       gmds::reduce_block_count(P.desc[k].n, P.desc[k].nb, P.T),
+                                                       gmds::reduce_block_count(P.desc[k].n, P.desc[k].nb, P.T, P.p),
                                                        P.desc[k].red_off, P.p, P.latent, P.T, gmds::kModeDescent, it,
                                                        s, ps.timer()));
             }
@@ -1117,7 +1117,7 @@ gini_status gini_stress_bwd_static(gini_ctx* c, const float* Delta, int64_t n, i
     hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, D, dd, D.instcnt);
     GINI_HIP(c, hipGetLastError());
     GINI_HIP(c, gmds::launch_stress_units(dd, 1, nt, 0, p, latent, T, true, GINI_LOSS_RAW, s));
-    GINI_HIP(c, gmds::launch_stress_reduce(dd, 1, gmds::reduce_block_count(D.n, D.nb, T), 0, p, latent, T,
+    GINI_HIP(c, gmds::launch_stress_reduce(dd, 1, gmds::reduce_block_count(D.n, D.nb, T, D.p), 0, p, latent, T,
                                            gmds::kModeGrad, 0, s));
     return GINI_OK;
 }

@@ -49,12 +49,16 @@ __host__ __device__ __forceinline__ int64_t tri_index(int64_t I, int64_t J, int6
 
 __host__ __device__ __forceinline__ int64_t tri_count(int64_t nb) { return nb * (nb + 1) / 2; }
 
-// Inverse of tri_index.
+// Inverse of tri_index.  Row I is the largest with tri_index(I, I) <= idx,
+// the smaller root of I^2 - (2nb+1) I + 2 idx = 0 rounded down.  The
+// discriminant is formed exactly in 64-bit integers and only its square root
+// is taken in FP32 (within a unit or two of the root for any nb < 2^26); the
+// integer fix-up that follows makes the result exact.
 __device__ __forceinline__ void tri_decode(int64_t idx, int64_t nb, int64_t& I, int64_t& J) {
-    // Row I starts at I*nb - I*(I-1)/2.  Start from the real root and fix up.
-    double b = 2.0 * (double)nb + 1.0;
-    double disc = b * b - 8.0 * (double)idx;
-    int64_t i = (int64_t)((b - sqrt(disc > 0.0 ? disc : 0.0)) * 0.5);
+    const int64_t b = 2 * nb + 1;
+    int64_t disc = b * b - 8 * idx;
+    if (disc < 0) disc = 0;
+    int64_t i = (b - (int64_t)sqrtf((float)disc)) / 2;
     if (i < 0) i = 0;
     if (i > nb - 1) i = nb - 1;
     while (i > 0 && tri_index(i, i, nb) > idx) --i;

@@ -51,14 +51,10 @@ hipError_t launch_stress_reduce(const InstDesc* dd, int n_inst, int64_t blocks, 
 }
 
 // Host mirror of reduce_blocks (must agree with the device functions above).
-int units_per_tile(int T) {
-    if (T == 64) return TileShape<64>::UNITS;
-    if (T == 128) return TileShape<128>::UNITS;
-    return TileShape<256>::UNITS;
-}
+int units_per_tile(int T, int p) { return T / unit_rows(T, p_bucket(p)); }
 
-int64_t reduce_block_count(int64_t n, int64_t nb, int T) {
-    const int64_t cnt = tri_count(nb) * units_per_tile(T) * kWaves;
+int64_t reduce_block_count(int64_t n, int64_t nb, int T, int p) {
+    const int64_t cnt = tri_count(nb) * units_per_tile(T, p) * kWaves;
     int64_t ns = (cnt + kVT * kBatch - 1) / (kVT * kBatch);
     ns = ns < 1 ? 1 : (ns > kSigSlices ? kSigSlices : ns);
     return ns + (n + kNPT - 1) / kNPT;

@@ -92,8 +92,8 @@ hipError_t launch_stress_units(const InstDesc* dd, int n_inst, int64_t count, in
 // is produced; `it` indexes sigma_hist in descent mode.
 hipError_t launch_stress_reduce(const InstDesc* dd, int n_inst, int64_t blocks, int64_t q_base, int p, int latent,
                                 int T, int mode, int it, hipStream_t s, LaunchTimer tm = {});
-int64_t reduce_block_count(int64_t n, int64_t nb, int T);
-int units_per_tile(int T);
+int64_t reduce_block_count(int64_t n, int64_t nb, int T, int p);
+int units_per_tile(int T, int p);
 // One launch: all instances, all iterations of the descent.
 hipError_t launch_solve_persistent(const InstDesc* dd, int n_inst, const int64_t* d_unit_prefix,
                                    int64_t units_per_iter, int iters, int p, int latent, int T, int loss, int grid,
@@ -132,6 +132,13 @@ hipError_t launch_rowmat(const float* A, int qa, const float* shift, float alpha
 // (median, sd) per column) may be null.  Y may alias X only if ldy == ldx.
 hipError_t launch_standardise(const float* X, int64_t n, int m, int64_t ldx, float* Y, int64_t ldy, float* stats,
                               hipStream_t s);
+
+// Rows of Delta one stress workgroup streams (a work unit): 64, or 128 for
+// p = 3 on tiles of at least 128 columns, where the heavier latent distance
+// makes the unit's fixed work (coordinates, partial sums) worth spreading
+// over twice the pairs (wider latent spaces would need more registers than
+// the longer unit saves).
+__host__ __device__ constexpr int unit_rows(int T, int p) { return (p == 3 && T >= 128) ? 128 : 64; }
 
 // Gradient components the stress kernels store per point in the tile
 // partials: the p = 2 Gini gradient is (-g, g), so one; p <= 4 has its own

@@ -51,15 +51,20 @@ typedef __attribute__((address_space(1))) float gflw;
 __device__ __forceinline__ gfl* gp(const float* p) { return (gfl*)p; }
 __device__ __forceinline__ gflw* gpw(float* p) { return (gflw*)p; }
 
-template <int T> struct TileShape {
+template <int T, int P> struct TileShape {
     static constexpr int CPT = T / kLPR;      // columns per thread
     static constexpr int NQ = CPT / 4;        // 16-byte loads per thread and row
-    static constexpr int UR = 64;             // rows per work unit
+    static constexpr int UR = unit_rows(T, P);  // rows per work unit
     static constexpr int STEPS = UR / kRPS;   // pipelined steps per unit
     static constexpr int UNITS = T / UR;      // work units per tile
     // Delta steps in flight per thread: the whole unit while that costs at
     // most 8 loads (32 registers), else two
     static constexpr int DEPTH = (NQ * STEPS <= 8) ? STEPS : 2;
+    // LDS of the row reduction: lane c4's sum of component c for unit row r
+    // at ((c * kLPR + c4) * RS + r) + c * PAD; the strides keep the writes of
+    // a half-wave and the reads of the final sums on distinct banks
+    static constexpr int RS = UR + 2;
+    static constexpr int PLANE = kLPR * RS + 11;
 };
 
 template <int P, int LAT>
@@ -226,7 +231,9 @@ __device__ Comp wg_sum(Comp v, float* lds) {
 // column reduction (16 row groups x T) and the stress tree.
 template <int P, int T>
 constexpr int unit_lds_floats() {
-    return TileShape<T>::UR * P + T * P + (kRPS * T > 2 * kWG ? kRPS * T : 2 * kWG);
+    constexpr int ROWS = P * TileShape<T, P>::PLANE;
+    constexpr int COLS = kRPS * T;
+    return TileShape<T, P>::UR * P + T * P + (ROWS > COLS ? ROWS : COLS);
 }
 
 // Stream unit `sub` (rows I*T + sub*UR ..) of tile lt = (I, J) of instance D:
@@ -234,11 +241,11 @@ constexpr int unit_lds_floats() {
 // and its stress, one (hi, lo) per wave: sigpart[(lt*UNITS + sub)*kWaves + w].
 template <int P, int LAT, int LOSS, int T, bool GRAD, bool MASK>
 __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int64_t J, float* lds) {
-    constexpr int CPT = TileShape<T>::CPT;
-    constexpr int NQ = TileShape<T>::NQ;
-    constexpr int UNITS = TileShape<T>::UNITS;
-    constexpr int UR = TileShape<T>::UR;
-    constexpr int STEPS = TileShape<T>::STEPS;
+    constexpr int CPT = TileShape<T, P>::CPT;
+    constexpr int NQ = TileShape<T, P>::NQ;
+    constexpr int UNITS = TileShape<T, P>::UNITS;
+    constexpr int UR = TileShape<T, P>::UR;
+    constexpr int STEPS = TileShape<T, P>::STEPS;
     constexpr int PG = PG_<P, LAT>::value;
     const int tid = threadIdx.x;
     const int c4 = tid % kLPR;
@@ -250,7 +257,7 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
     gfl* Zg = gp(D.Z);
     float* zrow = lds;                                  // [UR][P]
     float* zcol = lds + UR * P;                         // [T][P]
-    float* red = zcol + T * P;
+    float* red = zcol + T * P;                          // row sums during the steps, then the column sums
 
     // Delta loads for one step of the unit (unmasked: 16-byte global loads)
     // Masked tiles (the diagonal, and the last tile row or column) decide
@@ -307,7 +314,7 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
         const int64_t j = j0 + r;
         zc_[k] = (x < T * P && c < p && (!MASK || j < n)) ? Zg[j * D.ldz + c] : 0.f;
     }
-    constexpr int DEPTH = TileShape<T>::DEPTH;
+    constexpr int DEPTH = TileShape<T, P>::DEPTH;
     f4v buf[DEPTH][NQ];
 #pragma unroll
     for (int s = 0; s < DEPTH; ++s) load_step(s, buf[s]);
@@ -329,7 +336,7 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
 #pragma unroll
     for (int x = 0; x < CPT; ++x)
 #pragma unroll
-        for (int c = 0; c < PG; ++c) colacc[x][c] = 0.f;
+        for (int c = 0; c < PG; ++c) colacc[x][c] = -0.f;   // -0 + x == x: the first add folds away
     Comp sig;
 
     auto compute_step = [&](int s, const f4v (&buf)[NQ]) {
@@ -339,7 +346,7 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
         for (int c = 0; c < P; ++c) zi[c] = zrow[(s * kRPS + rr) * P + c];
         float rowacc[PG];
 #pragma unroll
-        for (int c = 0; c < PG; ++c) rowacc[c] = 0.f;
+        for (int c = 0; c < PG; ++c) rowacc[c] = -0.f;
         float sst = 0.f;
         // p = 2 Gini on an interior tile: unless some pair of the step is tied
         // (w = u2 - u1 = 0) somewhere in the wave, the gradient term is the
@@ -382,16 +389,17 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
             // coordinate differences d_ab = u_a - u_b, u_max - u_min is
             // max |d_ab| (the same rounded difference).  The gradient term is
             // +h on the largest coordinate, -h on the smallest and 0 on the
-            // middle one (h = a times the weighted residual): with s_ab = h/2
-            // carrying the sign of d_ab, the term of coordinate a is
-            // s_ab + s_ac, and h/2 + h/2 = h, h/2 - h/2 = 0 exactly, so each
-            // accumulated term equals the general rule's and no component is
-            // recovered from the others.  A tied pair (some d_ab == 0) or a
-            // pair outside the triangle gets r = 0 here and adds nothing; if
-            // some lane of the wave holds a tied pair of the triangle, the
-            // step's tied pairs then take the general midrank rule.
+            // middle one (h = a times the weighted residual rw).  The terms
+            // are accumulated in units of a/2, the reduction applying that
+            // factor once per point: with s_ab = rw carrying the sign of
+            // d_ab, the term of coordinate a is s_ab + s_ac, and rw + rw and
+            // rw - rw are exact, so every accumulated term is exact and no
+            // component is recovered from the others.  A tied pair (some
+            // d_ab == 0) or a pair outside the triangle gets r = 0 here and
+            // adds nothing; if some lane of the wave holds a tied pair of the
+            // triangle, the step's tied pairs then take the general midrank
+            // rule, converted to the same units.
             const float wmax = D.wtab[4];
-            const float whalf = 0.5f * wmax;
             bool tied = false;
 #pragma unroll
             for (int q = 0; q < NQ; ++q)
@@ -415,8 +423,7 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
                     const float rw = weigh<LOSS>(r, d);
                     sst = fmaf(r, rw, sst);
                     if constexpr (GRAD) {
-                        const float hh = rw * whalf;
-                        const float s01 = signed_as(hh, d01), s02 = signed_as(hh, d02), s12 = signed_as(hh, d12);
+                        const float s01 = signed_as(rw, d01), s02 = signed_as(rw, d02), s12 = signed_as(rw, d12);
                         const float g0 = s01 + s02, g1 = s12 - s01, g2 = -(s02 + s12);
                         rowacc[0] += g0;
                         rowacc[1] += g1;
@@ -427,6 +434,7 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
                     }
                 }
             if (__builtin_amdgcn_ballot_w64(tied) != 0) {
+                const float to_units = wmax > 0.f ? 2.f / wmax : 0.f;
 #pragma unroll
                 for (int q = 0; q < NQ; ++q)
 #pragma unroll
@@ -441,8 +449,8 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
                         if constexpr (GRAD) {
 #pragma unroll
                             for (int c = 0; c < PG; ++c) {
-                                rowacc[c] += g[c];
-                                colacc[x][c] += g[c];
+                                rowacc[c] += g[c] * to_units;
+                                colacc[x][c] += g[c] * to_units;
                             }
                         }
                     }
@@ -467,11 +475,10 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
                 }
         }
         if constexpr (GRAD) {
+            // the 16 lanes' sums of this row are added after the last step
+            constexpr int RS = TileShape<T, P>::RS, PLANE = TileShape<T, P>::PLANE;
 #pragma unroll
-            for (int c = 0; c < PG; ++c) {
-                const float tot = row16_sum(rowacc[c]);
-                if (c4 == 0 && (!MASK || il < rows_left)) gpw(D.rowpart)[(lt * T + il) * PG + c] = tot;
-            }
+            for (int c = 0; c < PG; ++c) red[c * PLANE + c4 * RS + s * kRPS + rr] = rowacc[c];
         }
         sig.add(sst);
     };
@@ -483,6 +490,20 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
     }
 
     if constexpr (GRAD) {
+        // row partials: the sums of the 16 lanes of each row, in lane order
+        {
+            constexpr int RS = TileShape<T, P>::RS, PLANE = TileShape<T, P>::PLANE;
+            __syncthreads();
+            for (int x = tid; x < UR * PG; x += kWG) {
+                const int rl = x / PG, c = x % PG;
+                const float* src = red + c * PLANE + rl;
+                float acc = src[0];
+#pragma unroll
+                for (int l = 1; l < kLPR; ++l) acc += src[l * RS];
+                const int il = sub * UR + rl;
+                if (!MASK || il < rows_left) gpw(D.rowpart)[(lt * T + il) * PG + c] = acc;
+            }
+        }
         // column partials: the 16 row groups hold partial sums of each column
 #pragma unroll
         for (int c = 0; c < PG; ++c) {
@@ -521,12 +542,12 @@ __device__ void unit_body(const InstDesc& D, int64_t lt, int sub, int64_t I, int
 
 template <int P, int LAT, int LOSS, int T, bool GRAD>
 __device__ __forceinline__ void stress_unit(const InstDesc& D, int64_t lu, float* lds) {
-    constexpr int UNITS = TileShape<T>::UNITS;
+    constexpr int UNITS = TileShape<T, P>::UNITS;
     const int64_t lt = lu / UNITS;
     const int sub = (int)(lu % UNITS);
     int64_t I, J;
     tri_decode(lt, D.nb, I, J);
-    if (I * T + (int64_t)sub * TileShape<T>::UR >= D.n) return;   // rows past n: nothing to do
+    if (I * T + (int64_t)sub * TileShape<T, P>::UR >= D.n) return;   // rows past n: nothing to do
     const bool interior = D.vec && (I < J) && ((J + 1) * T <= D.n);
     if (interior) unit_body<P, LAT, LOSS, T, GRAD, false>(D, lt, sub, I, J, lds);
     else unit_body<P, LAT, LOSS, T, GRAD, true>(D, lt, sub, I, J, lds);
@@ -560,7 +581,7 @@ __host__ __device__ constexpr int red_batch(int pg) { return pg <= 2 ? 8 : (pg <
 template <int P, int LAT, int T>
 __device__ __forceinline__ void point_partial(const InstDesc& D, int64_t k, int s, Comp (&acc)[PG_<P, LAT>::value]) {
     constexpr int PG = PG_<P, LAT>::value;
-    constexpr int UNITS = TileShape<T>::UNITS;
+    constexpr int UNITS = TileShape<T, P>::UNITS;
     constexpr int RB = red_batch(PG);
     // Tile and unit indices fit 32 bits: the host caps an instance's work
     // units at 2^31 - 1, so nb^2 < 2^32; element offsets are taken in 64 bits.
@@ -585,7 +606,7 @@ __device__ __forceinline__ void point_partial(const InstDesc& D, int64_t k, int 
                 const uint32_t u = tc % UNITS;
                 const uint32_t lt = I * nb - (I * (I - 1)) / 2 + (b - I);
                 // units past n (only in the last tile) were never written
-                const bool ok = (t < nterm) && !(I == nb - 1 && (int64_t)I * T + (int64_t)u * TileShape<T>::UR >= D.n);
+                const bool ok = (t < nterm) && !(I == nb - 1 && (int64_t)I * T + (int64_t)u * TileShape<T, P>::UR >= D.n);
                 const uint64_t off = (uint64_t)(lt * UNITS + u) * (T * PG);
 #pragma unroll
                 for (int c = 0; c < PG; ++c) v[q][c] = ok ? -cbase[off + c] : 0.f;
@@ -651,6 +672,11 @@ __device__ void reduce_group(const InstDesc& D, int64_t k0, int mode, float* lds
             const float v = loss_factor(D) * D.c2 * tot[0].value();
             G[0] = -v;
             G[1] = v;
+        } else if constexpr (P == 3 && LAT == 0) {
+            // the p = 3 Gini terms were accumulated in units of a/2 (a = (3/2) W_3[6])
+            const float f = loss_factor(D) * (0.5f * D.wtab[4]);
+#pragma unroll
+            for (int c = 0; c < P; ++c) G[c] = f * tot[c].value();
         } else {
 #pragma unroll
             for (int c = 0; c < P; ++c) G[c] = loss_factor(D) * tot[c].value();
@@ -674,26 +700,26 @@ __device__ void reduce_group(const InstDesc& D, int64_t k0, int mode, float* lds
 // then a fixed binary tree over the kVT values; slices are added in order
 // (at most kSigSlices of them, the room the host reserves per instance).
 
-template <int T>
+template <int T, int P>
 __device__ __forceinline__ int64_t sigma_count(const InstDesc& D) {
-    return tri_count(D.nb) * TileShape<T>::UNITS * kWaves;
+    return tri_count(D.nb) * TileShape<T, P>::UNITS * kWaves;
 }
 // At most kVT * kBatch partials per slice (one batch of loads per virtual
 // thread), at most kSigSlices slices (one slice -- written directly, no
 // combining step -- for small instances).
-template <int T>
+template <int T, int P>
 __device__ __forceinline__ int sigma_slices(const InstDesc& D) {
-    const int64_t s = (sigma_count<T>(D) + kVT * kBatch - 1) / (kVT * kBatch);
+    const int64_t s = (sigma_count<T, P>(D) + kVT * kBatch - 1) / (kVT * kBatch);
     return (int)(s < 1 ? 1 : (s > kSigSlices ? kSigSlices : s));
 }
 
 // LDS: 2 * kVT floats.  All NT threads return the slice sum.
-template <int T, int NT>
+template <int T, int P, int NT>
 __device__ Comp sigma_slice(const InstDesc& D, int slice, float* lds) {
-    constexpr int UNITS = TileShape<T>::UNITS;
+    constexpr int UNITS = TileShape<T, P>::UNITS;
     const int64_t nt = tri_count(D.nb);
-    const int64_t cnt = sigma_count<T>(D);
-    const int ns = sigma_slices<T>(D);
+    const int64_t cnt = sigma_count<T, P>(D);
+    const int ns = sigma_slices<T, P>(D);
     const int64_t a = cnt * slice / ns;
     const int64_t e = cnt * (slice + 1) / ns;
     gfl* sp = gp(D.sigpart);
@@ -706,7 +732,7 @@ __device__ Comp sigma_slice(const InstDesc& D, int slice, float* lds) {
                 const int64_t t = t0 + (int64_t)q * kVT;
                 const int64_t lu = t / kWaves;
                 const int u = (int)(lu % UNITS);
-                const bool ok = (t < e) && !(lu / UNITS == nt - 1 && (D.nb - 1) * T + (int64_t)u * TileShape<T>::UR >= D.n);
+                const bool ok = (t < e) && !(lu / UNITS == nt - 1 && (D.nb - 1) * T + (int64_t)u * TileShape<T, P>::UR >= D.n);
                 hv[q] = ok ? sp[2 * t] : 0.f;
                 lv[q] = ok ? sp[2 * t + 1] : 0.f;
             }
@@ -765,12 +791,12 @@ __device__ Comp sigma_slice(const InstDesc& D, int slice, float* lds) {
     return r;
 }
 
-template <int T, int NT>
+template <int T, int P, int NT>
 __device__ Comp instance_sigma(const InstDesc& D, float* lds) {
-    const int ns = sigma_slices<T>(D);
-    if (ns == 1) return sigma_slice<T, NT>(D, 0, lds);
+    const int ns = sigma_slices<T, P>(D);
+    if (ns == 1) return sigma_slice<T, P, NT>(D, 0, lds);
     Comp tot;
-    for (int sl = 0; sl < ns; ++sl) tot.add(sigma_slice<T, NT>(D, sl, lds));
+    for (int sl = 0; sl < ns; ++sl) tot.add(sigma_slice<T, P, NT>(D, sl, lds));
     return tot;
 }
 
@@ -855,9 +881,9 @@ __global__ __launch_bounds__(kRedWG) void k_stress_reduce(const InstDesc* __rest
     }
     const InstDesc& D = dd[lo];
     const int64_t b = q - D.red_off;
-    const int ns = sigma_slices<T>(D);
+    const int ns = sigma_slices<T, P>(D);
     if (b < ns) {
-        const Comp part = sigma_slice<T, kRedWG>(D, (int)b, lds);
+        const Comp part = sigma_slice<T, P, kRedWG>(D, (int)b, lds);
         if (threadIdx.x == 0) {
             if (ns == 1) {
                 write_sigma(D, mode, it, part);
@@ -905,7 +931,7 @@ __global__ __launch_bounds__(kWG) void k_solve_persistent(const InstDesc* __rest
                                                           int64_t per_iter, int iters, SolveCtl* ctl,
                                                           uint32_t* epoch, int64_t spin_limit) {
     constexpr int PG = PG_<P, LAT>::value;
-    constexpr int UNITS = TileShape<T>::UNITS;
+    constexpr int UNITS = TileShape<T, P>::UNITS;
     constexpr int NL1 = unit_lds_floats<P, T>();
     constexpr int NL2 = reduce_lds_floats<PG>();
     __shared__ float lds[NL1 > NL2 ? NL1 : NL2];
@@ -971,7 +997,7 @@ __global__ __launch_bounds__(kWG) void k_solve_persistent(const InstDesc* __rest
         __syncthreads();
         if (sh_flag) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            const Comp s = instance_sigma<T, kWG>(D, lds);
+            const Comp s = instance_sigma<T, P, kWG>(D, lds);
             write_sigma(D, kModeDescent, it, s);
             for (int64_t k0 = 0; k0 < D.n; k0 += kNPT) reduce_group<P, LAT, T, kWG>(D, k0, kModeDescent, lds);
             __threadfence();

@@ -40,7 +40,7 @@ def test_static_entry_matches_the_allocating_one(gm, first, second):
 
 
 def test_static_entry_refuses_what_does_not_fit(gm):
-    n = 21600                                   # p = 3 needs more than the 64 MiB array
+    n = 40000                                   # p = 3 needs about 150 MB of scratch, over the 64 MiB array
     D = torch.empty((n, n), device=DEV)
     Z = torch.zeros((n, 3), device=DEV)
     with pytest.raises(gm.GiniError) as e:
