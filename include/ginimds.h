@@ -299,6 +299,10 @@ gini_status gini_mds_solve(gini_ctx* ctx, const gini_instance* inst, int32_t n_i
  * instances over `probe_iters` iterations each, on copies of the
  * configurations (the caller's Z and histories are not modified), and write
  * the fastest into *best (flags keep the caller's CHECK_FINITE bit).  The
+ * candidates are the batched mode at every tile size, and the persistent mode
+ * at several grid sizes only where one iteration has no more work units than
+ * the GPU has compute units (elsewhere its per-unit release costs more than
+ * two launches per iteration).  The
  * result is cached in the context, keyed by the batch's shape, and used by
  * gini_mds_solve with GINI_SOLVE_AUTOTUNE.  Synchronises `stream`.
  */

@@ -83,6 +83,12 @@ struct gini_ctx {
     // gini_select_nu: the folds' dissimilarities and the small result buffers
     float* sel = nullptr;
     size_t sel_bytes = 0;
+    // gini_classical_mds: pinned landing slots for the Rayleigh-Ritz matrices
+    // of the iterations in flight, and their events
+    float* cm_pin = nullptr;
+    hipEvent_t cm_ev[4] = {};
+    hipEvent_t cm_ready[4] = {};
+    hipStream_t cm_copy = nullptr;   // the copies to the landing slots run beside the iteration
 };
 
 namespace {
@@ -503,7 +509,7 @@ gini_status stress_common(gini_ctx* c, const float* Delta, int64_t n, int64_t ld
     {
         ProfScope ps(c, kProfReduce, s, true);
         GINI_HIP(c, gmds::launch_stress_reduce(ddp, 1, rblocks, 0, p, latent, T,
-                                               grad ? gmds::kModeGrad : gmds::kModeSigma, 0, s, ps.timer()));
+                                               grad ? gmds::kModeGrad : gmds::kModeSigma, 0, n, s, ps.timer()));
     }
     return slot_done(c, sl, s);
 }
@@ -515,6 +521,8 @@ struct Plan {
     std::vector<int64_t> prefix;    // work-unit prefix, n_inst + 1
     int64_t tiles = 0;              // work units per iteration
     int64_t rblocks = 0;            // reduction blocks per iteration
+    int64_t maxn = 0;               // largest instance
+    std::vector<int32_t> bmap;      // instance of every reduction block (batched launches)
     int p = 0, latent = 0, T = 0, loss = 0;
 };
 
@@ -592,10 +600,18 @@ gini_status make_plan(gini_ctx* c, const gini_instance* inst, int32_t n_inst, in
         P.prefix[k + 1] = P.prefix[k] + nt;
         D.red_off = P.rblocks;
         P.rblocks += gmds::reduce_block_count(D.n, D.nb, T, D.p);
+        P.maxn = std::max(P.maxn, D.n);
         floats += partial_floats(D, T, pg);
         floats = (floats + 63) & ~size_t(63);
     }
     P.tiles = P.prefix[n_inst];
+    if (n_inst > 1) {
+        P.bmap.resize(P.rblocks);
+        for (int k = 0; k < n_inst; ++k) {
+            const int64_t b1 = k + 1 < n_inst ? P.desc[k + 1].red_off : P.rblocks;
+            for (int64_t b = P.desc[k].red_off; b < b1; ++b) P.bmap[b] = k;
+        }
+    }
     if (P.tiles > (int64_t)0x7fffffff) return fail(c, GINI_EUNSUPPORTED, "too many tiles in one solve");
     gini_status st = ensure_scratch(c, floats * sizeof(float));
     if (st != GINI_OK) return st;
@@ -627,15 +643,20 @@ gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStr
     const int n_inst = (int)P.desc.size();
     // one upload: descriptors, then the tile prefix
     const size_t dbytes = (P.desc.size() * sizeof(InstDesc) + 15) & ~size_t(15);
-    std::vector<unsigned char> blob(dbytes + P.prefix.size() * sizeof(int64_t));
+    const size_t pbytes = P.prefix.size() * sizeof(int64_t);
+    std::vector<unsigned char> blob(dbytes + pbytes + P.bmap.size() * sizeof(int32_t));
     std::memcpy(blob.data(), P.desc.data(), P.desc.size() * sizeof(InstDesc));
-    std::memcpy(blob.data() + dbytes, P.prefix.data(), P.prefix.size() * sizeof(int64_t));
+    std::memcpy(blob.data() + dbytes, P.prefix.data(), pbytes);
+    if (!P.bmap.empty()) std::memcpy(blob.data() + dbytes + pbytes, P.bmap.data(), P.bmap.size() * sizeof(int32_t));
     void* dd = nullptr;
     Slot* sl = nullptr;
     gini_status st = upload(c, blob.data(), blob.size(), s, &dd, &sl);
     if (st != GINI_OK) return st;
     const InstDesc* ddp = static_cast<const InstDesc*>(dd);
     const int64_t* dprefix = reinterpret_cast<const int64_t*>(static_cast<unsigned char*>(dd) + dbytes);
+    const int32_t* dbmap = P.bmap.empty() ? nullptr
+                                          : reinterpret_cast<const int32_t*>(static_cast<unsigned char*>(dd) + dbytes +
+                                                                             pbytes);
     if (mode == GINI_SOLVE_PERSISTENT) {
         st = ensure_ctl(c, n_inst);
         if (st != GINI_OK) return st;
@@ -654,7 +675,7 @@ gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStr
                 GINI_HIP(c, gmds::launch_stress_reduce(ddp + k, 1,
                                                        gmds::reduce_block_count(P.desc[k].n, P.desc[k].nb, P.T, P.p),
                                                        P.desc[k].red_off, P.p, P.latent, P.T, gmds::kModeDescent, it,
-                                                       s, ps.timer()));
+                                                       P.desc[k].n, s, ps.timer()));
             }
         }
     } else if (mode == GINI_SOLVE_BATCHED) {
@@ -666,7 +687,7 @@ gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStr
             }
             ProfScope ps(c, kProfReduce, s, true);
             GINI_HIP(c, gmds::launch_stress_reduce(ddp, n_inst, P.rblocks, 0, P.p, P.latent, P.T,
-                                                   gmds::kModeDescent, it, s, ps.timer()));
+                                                   gmds::kModeDescent, it, P.maxn, s, ps.timer(), dbmap));
         }
     } else {
         hipLaunchKernelGGL(k_reset_ctl, dim3((n_inst + 255) / 256), dim3(256), 0, s, c->ctl, c->epochs, n_inst);
@@ -744,9 +765,19 @@ gini_status autotune_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst
     std::vector<gini_solve_opts> cand;
     int64_t maxn = 0;
     for (int k = 0; k < n_inst; ++k) maxn = std::max(maxn, inst[k].n);
+    // The persistent solver pays a device-scope release (a writeback of the
+    // XCD's L2) per work unit; it can only win when an iteration is one wave
+    // of workgroups or less and launch latency dominates, so it is tried only
+    // there.
     for (int T : {64, 128, 256}) {
         if (T > 64 && maxn <= T / 2) continue;
         cand.push_back({probe_iters, GINI_SOLVE_BATCHED, T, 0});
+        int64_t units = 0;
+        for (int k = 0; k < n_inst; ++k) {
+            const int64_t nb = (inst[k].n + T - 1) / T;
+            units += gmds::tri_count(nb) * gmds::units_per_tile(T, inst[k].p);
+        }
+        if (units > c->cus) continue;
         int nb = gmds::persistent_max_blocks_per_cu(inst[0].p, inst[0].latent, T, inst[0].loss);
         for (int g : {1, 2, 4, 8}) {
             if (g > nb) break;
@@ -926,6 +957,12 @@ void gini_destroy(gini_ctx* c) {
         }
         if (c->cnt) (void)hipFree(c->cnt);
         if (c->sel) (void)hipFree(c->sel);
+        if (c->cm_pin) (void)hipHostFree(c->cm_pin);
+        for (hipEvent_t e : c->cm_ev)
+            if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : c->cm_ready)
+            if (e) (void)hipEventDestroy(e);
+        if (c->cm_copy) (void)hipStreamDestroy(c->cm_copy);
         prof_clear(c);
         for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
         for (auto& sl : c->ring) {
@@ -1118,7 +1155,7 @@ gini_status gini_stress_bwd_static(gini_ctx* c, const float* Delta, int64_t n, i
     GINI_HIP(c, hipGetLastError());
     GINI_HIP(c, gmds::launch_stress_units(dd, 1, nt, 0, p, latent, T, true, GINI_LOSS_RAW, s));
     GINI_HIP(c, gmds::launch_stress_reduce(dd, 1, gmds::reduce_block_count(D.n, D.nb, T, D.p), 0, p, latent, T,
-                                           gmds::kModeGrad, 0, s));
+                                           gmds::kModeGrad, 0, D.n, s));
     return GINI_OK;
 }
 
@@ -1226,8 +1263,8 @@ static gini_status eval_sigma_batch(gini_ctx* c, const gini_instance* inst, int 
     }
     {
         ProfScope ps(c, kProfReduce, s, true);
-        GINI_HIP(c, gmds::launch_stress_reduce(ddp, n_inst, P.rblocks, 0, P.p, P.latent, T, gmds::kModeSigma, 0, s,
-                                               ps.timer()));
+        GINI_HIP(c, gmds::launch_stress_reduce(ddp, n_inst, P.rblocks, 0, P.p, P.latent, T, gmds::kModeSigma, 0,
+                                               P.maxn, s, ps.timer()));
     }
     return slot_done(c, sl, s);
 }
@@ -1481,136 +1518,136 @@ gini_status gini_classical_mds(gini_ctx* c, const float* Delta, int64_t n, int64
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int q = (int)std::min<int64_t>({(int64_t)gmds::kMaxCmdsQ, (int64_t)p + 4, n - 1});
     const int Q = gmds::kMaxCmdsQ;
-    // workspace: V, Y' (D^2 V), Yh (B V), then small buffers
-    const size_t nq = (size_t)n * q;
-    const size_t small = 2 * (size_t)Q * Q + 2 * (size_t)Q * Q + Q;
-    const size_t parts = 2 * (size_t)Q * Q * gmds::gram_blocks(n);
-    st = ensure_select(c, (3 * nq + small + parts + 64) * sizeof(float));
+    constexpr int kSlots = 4;                  // Rayleigh-Ritz matrices in flight (ring)
+    constexpr int kVRing = 3;                  // blocks V_t kept: the one being checked and two ahead
+    // workspace: the V ring, Y' (D^2 V), Yh (B V), then small buffers
+    const size_t nq = ((size_t)n * q + 63) & ~size_t(63);
+    const size_t small = 2 * (size_t)Q * Q * (2 + kSlots) + 2 * (size_t)Q * Q;
+    st = ensure_select(c, ((kVRing + 2) * nq + small + gmds::gram_part_floats() + 64) * sizeof(float));
     if (st != GINI_OK) return st;
-    float* V = c->sel;
-    float* Yp = V + nq;
+    if (!c->cm_pin) {
+        if (hipHostMalloc(reinterpret_cast<void**>(&c->cm_pin), 2 * (size_t)Q * Q * kSlots * sizeof(float),
+                          hipHostMallocDefault) != hipSuccess)
+            return fail(c, GINI_ENOMEM, "pinned landing buffer of classical MDS failed");
+        for (auto& e : c->cm_ev) GINI_HIP(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        for (auto& e : c->cm_ready) GINI_HIP(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        GINI_HIP(c, hipStreamCreateWithFlags(&c->cm_copy, hipStreamNonBlocking));
+    }
+    float* Vr[kVRing];
+    for (int k = 0; k < kVRing; ++k) Vr[k] = c->sel + k * nq;
+    float* Yp = c->sel + kVRing * nq;
     float* Yh = Yp + nq;
-    float* gout = Yh + nq;                     // Q*Q (hi, lo)
-    float* Mdev = gout + 2 * (size_t)Q * Q;    // Q*Q
-    float* Idev = Mdev + (size_t)Q * Q;        // Q*Q identity (q x q)
-    float* shift = Idev + (size_t)Q * Q;       // Q
-    float* part = shift + Q;
-    std::vector<float> hg(2 * (size_t)Q * Q), hm((size_t)Q * Q);
-    auto fetch = [&](int ne, std::vector<double>& out) -> gini_status {
-        GINI_HIP(c, hipMemcpyAsync(hg.data(), gout, 2 * (size_t)ne * sizeof(float), hipMemcpyDeviceToHost, s));
-        GINI_HIP(c, hipStreamSynchronize(s));
-        out.resize(ne);
-        for (int e = 0; e < ne; ++e) out[e] = (double)hg[2 * e] + (double)hg[2 * e + 1];
-        return GINI_OK;
-    };
-    auto put = [&](float* dst, const std::vector<double>& v) -> gini_status {
-        for (size_t k = 0; k < v.size(); ++k) hm[k] = (float)v[k];
-        GINI_HIP(c, hipMemcpyAsync(dst, hm.data(), v.size() * sizeof(float), hipMemcpyHostToDevice, s));
-        GINI_HIP(c, hipStreamSynchronize(s));      // hm is reused at once
-        return GINI_OK;
-    };
-    // Orthonormalise the centred block A (n x q) into V: eigen-decompose its
-    // Gram matrix G = W S W^T and map V = A W S^(-1/2); directions with
-    // S below 1e-12 of the largest become zero columns (a rank-deficient B).
-    auto orthonormalise = [&](const float* A) -> gini_status {
-        GINI_HIP(c, gmds::launch_gram(A, q, A, q, n, part, gout, s));
-        std::vector<double> G, lam, W;
-        gini_status e = fetch(q * q, G);
-        if (e != GINI_OK) return e;
-        for (int i = 0; i < q; ++i)
-            for (int j = 0; j < i; ++j) G[(size_t)i * q + j] = G[(size_t)j * q + i] = 0.5 * (G[(size_t)i * q + j] + G[(size_t)j * q + i]);
-        jacobi_eig(q, G, lam, W);
-        double mx = 0.0;
-        for (double v : lam) mx = std::max(mx, v);
-        std::vector<double> M((size_t)q * q, 0.0);
-        for (int k = 0; k < q; ++k) {
-            if (!(lam[k] > 1e-12 * mx) || !(mx > 0.0)) continue;
-            const double sc = 1.0 / std::sqrt(lam[k]);
-            for (int i = 0; i < q; ++i) M[(size_t)i * q + k] = W[(size_t)i * q + k] * sc;
-        }
-        e = put(Mdev, M);
-        if (e != GINI_OK) return e;
-        GINI_HIP(c, gmds::launch_rowmat(A, q, nullptr, 1.f, Mdev, q, n, V, q, s));
-        return GINI_OK;
-    };
-    // start: a fixed pseudo-random block (xorshift64*), centred
+    float* gout = Yh + nq;                         // column sums (hi, lo)
+    float* gG = gout + 2 * (size_t)Q * Q;          // Gram matrix of B V (hi, lo)
+    float* gT = gG + 2 * (size_t)Q * Q;            // kSlots Rayleigh-Ritz matrices (hi, lo)
+    float* Mdev = gT + 2 * (size_t)Q * Q * kSlots; // orthonormalising map, q x q
+    float* Idev = Mdev + (size_t)Q * Q;            // identity, q x q
+    float* part = Idev + (size_t)Q * Q;            // Gram partials
     {
-        std::vector<float> v0(nq);
+        std::vector<float> I((size_t)q * q, 0.f);
+        for (int i = 0; i < q; ++i) I[(size_t)i * q + i] = 1.f;
+        void* dI = nullptr;
+        Slot* sl = nullptr;
+        st = upload(c, I.data(), I.size() * sizeof(float), s, &dI, &sl);
+        if (st != GINI_OK) return st;
+        GINI_HIP(c, hipMemcpyAsync(Idev, dI, I.size() * sizeof(float), hipMemcpyDeviceToDevice, s));
+        st = slot_done(c, sl, s);
+        if (st != GINI_OK) return st;
+    }
+    // start: a fixed pseudo-random block (xorshift64*), centred, orthonormalised
+    // (Cholesky of its Gram matrix, on the device)
+    {
+        std::vector<float> v0((size_t)n * q);
         uint64_t x = 0x9E3779B97F4A7C15ull;
-        for (size_t k = 0; k < nq; ++k) {
+        for (size_t k = 0; k < v0.size(); ++k) {
             x ^= x >> 12;
             x ^= x << 25;
             x ^= x >> 27;
             v0[k] = (float)((double)((x * 0x2545F4914F6CDD1Dull) >> 11) * (1.0 / 9007199254740992.0) - 0.5);
         }
-        GINI_HIP(c, hipMemcpyAsync(Yp, v0.data(), nq * sizeof(float), hipMemcpyHostToDevice, s));
+        GINI_HIP(c, hipMemcpyAsync(Yp, v0.data(), v0.size() * sizeof(float), hipMemcpyHostToDevice, s));
         GINI_HIP(c, gmds::launch_gram(Yp, q, nullptr, 1, n, part, gout, s));
-        std::vector<double> cs;
-        st = fetch(q, cs);
-        if (st != GINI_OK) return st;
-        for (auto& v : cs) v /= (double)n;
-        st = put(shift, cs);
-        if (st != GINI_OK) return st;
-        std::vector<double> I((size_t)q * q, 0.0);
-        for (int i = 0; i < q; ++i) I[(size_t)i * q + i] = 1.0;
-        st = put(Idev, I);
-        if (st != GINI_OK) return st;
-        GINI_HIP(c, gmds::launch_rowmat(Yp, q, shift, 1.f, Idev, q, n, Yh, q, s));
-        st = orthonormalise(Yh);
-        if (st != GINI_OK) return st;
+        GINI_HIP(c, gmds::launch_rowmat(Yp, q, gout, 1.f, Idev, q, n, Yh, q, s));
+        GINI_HIP(c, gmds::launch_gram(Yh, q, Yh, q, n, part, gG, s));
+        GINI_HIP(c, gmds::launch_chol_orth(gG, q, Mdev, s));
+        GINI_HIP(c, gmds::launch_rowmat(Yh, q, nullptr, 1.f, Mdev, q, n, Vr[0], q, s));
+        GINI_HIP(c, hipStreamSynchronize(s));      // v0 is host memory
     }
-    std::vector<double> lam, W, prev;
-    int it = 0;
-    for (; it < max_iters; ++it) {
-        // Yh = B V = -1/2 H (D^2 V)
+    // Step t on the device: Yh = B V_t = -1/2 H (D^2 V_t), the Rayleigh-Ritz
+    // matrix T_t = V_t^T Yh (sent to the host ring) and G = Yh^T Yh in one
+    // launch, V_{t+1} = Yh R^-1 from the Cholesky factor of G.  The host checks
+    // step t while step t+1 runs, so the GPU never waits for it; V_t stays in
+    // the ring until then.
+    auto enqueue = [&](int t) -> gini_status {
+        const float* V = Vr[t % kVRing];
+        float* T = gT + 2 * (size_t)Q * Q * (t % kSlots);
         GINI_HIP(c, gmds::launch_d2v(Delta, n, ldd, V, q, Yp, s));
         GINI_HIP(c, gmds::launch_gram(Yp, q, nullptr, 1, n, part, gout, s));
-        GINI_HIP(c, gmds::launch_colmean(gout, q, n, shift, s));      // centring stays on the device
-        GINI_HIP(c, gmds::launch_rowmat(Yp, q, shift, -0.5f, Idev, q, n, Yh, q, s));
-        // Rayleigh-Ritz on span(V): T = V^T B V
-        GINI_HIP(c, gmds::launch_gram(V, q, Yh, q, n, part, gout, s));
-        std::vector<double> T;
-        st = fetch(q * q, T);
-        if (st != GINI_OK) return st;
+        GINI_HIP(c, gmds::launch_rowmat(Yp, q, gout, -0.5f, Idev, q, n, Yh, q, s));
+        GINI_HIP(c, gmds::launch_gram(V, q, Yh, q, n, part, T, s, Yh, Yh, gG));
+        float* land = c->cm_pin + 2 * (size_t)Q * Q * (t % kSlots);
+        GINI_HIP(c, hipEventRecord(c->cm_ready[t % kSlots], s));
+        GINI_HIP(c, hipStreamWaitEvent(c->cm_copy, c->cm_ready[t % kSlots], 0));
+        GINI_HIP(c, hipMemcpyAsync(land, T, 2 * (size_t)q * q * sizeof(float), hipMemcpyDeviceToHost, c->cm_copy));
+        GINI_HIP(c, hipEventRecord(c->cm_ev[t % kSlots], c->cm_copy));
+        GINI_HIP(c, gmds::launch_chol_orth(gG, q, Mdev, s));
+        GINI_HIP(c, gmds::launch_rowmat(Yh, q, nullptr, 1.f, Mdev, q, n, Vr[(t + 1) % kVRing], q, s));
+        return GINI_OK;
+    };
+    std::vector<double> lam, W, prev;
+    int enq = 0, chk = 0;
+    for (;;) {
+        while (enq < max_iters && enq <= chk + 1) {
+            st = enqueue(enq++);
+            if (st != GINI_OK) return st;
+        }
+        GINI_HIP(c, hipEventSynchronize(c->cm_ev[chk % kSlots]));
+        const float* g = c->cm_pin + 2 * (size_t)Q * Q * (chk % kSlots);
+        std::vector<double> T((size_t)q * q);
         for (int i = 0; i < q; ++i)
-            for (int j = 0; j < i; ++j) T[(size_t)i * q + j] = T[(size_t)j * q + i] = 0.5 * (T[(size_t)i * q + j] + T[(size_t)j * q + i]);
+            for (int j = 0; j < q; ++j) T[(size_t)i * q + j] = (double)g[2 * (i * q + j)] + (double)g[2 * (i * q + j) + 1];
+        for (int i = 0; i < q; ++i)
+            for (int j = 0; j < i; ++j)
+                T[(size_t)i * q + j] = T[(size_t)j * q + i] = 0.5 * (T[(size_t)i * q + j] + T[(size_t)j * q + i]);
         jacobi_eig(q, T, lam, W);
         std::vector<double> top(lam);
         std::sort(top.begin(), top.end(), std::greater<double>());
         top.resize(p);
-        bool done = false;
+        bool done = chk + 1 >= max_iters;
         if (!prev.empty()) {
             double scale = 0.0, diff = 0.0;
             for (int k = 0; k < p; ++k) {
                 scale = std::max(scale, std::fabs(top[k]));
                 diff = std::max(diff, std::fabs(top[k] - prev[k]));
             }
-            done = diff <= tol * scale;
+            done = done || diff <= tol * scale;
         }
         prev = top;
-        if (done) {
-            ++it;
-            break;
-        }
-        st = orthonormalise(Yh);                   // V <- orth(B V)
-        if (st != GINI_OK) return st;
+        if (done) break;
+        ++chk;
     }
-    // the p Ritz pairs with the largest eigenvalues: Z = V W_p diag(sqrt(max(lam, 0)))
+    // the p Ritz pairs of step chk with the largest eigenvalues: Z = V_chk W_p diag(sqrt(max(lam, 0)))
     std::vector<int> idx(q);
     std::iota(idx.begin(), idx.end(), 0);
     std::stable_sort(idx.begin(), idx.end(), [&](int a2, int b2) { return lam[a2] > lam[b2]; });
-    std::vector<double> M((size_t)q * p, 0.0);
+    std::vector<float> M((size_t)q * p, 0.f);
     for (int k = 0; k < p; ++k) {
         const int j = idx[k];
         const double sc = std::sqrt(std::max(lam[j], 0.0));
-        for (int i = 0; i < q; ++i) M[(size_t)i * p + k] = W[(size_t)i * q + j] * sc;
+        for (int i = 0; i < q; ++i) M[(size_t)i * p + k] = (float)(W[(size_t)i * q + j] * sc);
         if (eigvals) eigvals[k] = lam[j];
     }
-    st = put(Mdev, M);
+    void* dM = nullptr;
+    Slot* sl = nullptr;
+    st = upload(c, M.data(), M.size() * sizeof(float), s, &dM, &sl);
     if (st != GINI_OK) return st;
-    GINI_HIP(c, gmds::launch_rowmat(V, q, nullptr, 1.f, Mdev, p, n, Z, ldz, s));
+    GINI_HIP(c, gmds::launch_rowmat(Vr[chk % kVRing], q, nullptr, 1.f, static_cast<const float*>(dM), p, n, Z, ldz,
+                                    s));
+    st = slot_done(c, sl, s);
+    if (st != GINI_OK) return st;
     GINI_HIP(c, hipStreamSynchronize(s));
-    if (iters_done) *iters_done = it;
+    GINI_HIP(c, hipStreamSynchronize(c->cm_copy));   // no copy outlives the call
+    if (iters_done) *iters_done = chk + 1;
     for (int k = 0; k < p; ++k)
         if (eigvals && !std::isfinite(eigvals[k])) return fail(c, GINI_ENOTFINITE, "eigenvalue %d is not finite", k);
     return GINI_OK;

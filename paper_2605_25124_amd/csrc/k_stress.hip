@@ -11,29 +11,33 @@ __global__ void k_fill_u32(uint32_t* p, int64_t count, uint32_t v) {
 }
 
 template <int P, int LAT, int T>
-static hipError_t reduce_impl(const InstDesc* dd, int n_inst, int64_t blocks, int64_t qb, int mode, int it,
-                              const Launch& L) {
+static hipError_t reduce_impl(const InstDesc* dd, int n_inst, const int32_t* bmap, int64_t blocks, int64_t qb,
+                              int mode, int it, const Launch& L) {
     if (blocks <= 0) return hipSuccess;
-    return launch_k(k_stress_reduce<P, LAT, T>, dim3((unsigned)blocks), dim3(kRedWG), L, dd, n_inst, qb, mode, it);
+    if (L.small)
+        return launch_k(k_stress_reduce<P, LAT, T, kRedWGSmall>, dim3((unsigned)blocks), dim3(kRedWGSmall), L, dd,
+                        n_inst, bmap, qb, mode, it);
+    return launch_k(k_stress_reduce<P, LAT, T, kRedWG>, dim3((unsigned)blocks), dim3(kRedWG), L, dd, n_inst, bmap,
+                    qb, mode, it);
 }
 
 template <int LAT, int T>
-static hipError_t reduce_dispatch_p(const InstDesc* dd, int n_inst, int64_t blocks, int64_t qb, int p, int mode,
-                                    int it, const Launch& L) {
+static hipError_t reduce_dispatch_p(const InstDesc* dd, int n_inst, const int32_t* bmap, int64_t blocks, int64_t qb,
+                                    int p, int mode, int it, const Launch& L) {
     switch (p_bucket(p)) {
-        case 1: return reduce_impl<1, LAT, T>(dd, n_inst, blocks, qb, mode, it, L);
-        case 2: return reduce_impl<2, LAT, T>(dd, n_inst, blocks, qb, mode, it, L);
-        case 3: return reduce_impl<3, LAT, T>(dd, n_inst, blocks, qb, mode, it, L);
-        case 4: return reduce_impl<4, LAT, T>(dd, n_inst, blocks, qb, mode, it, L);
-        default: return reduce_impl<kMaxP, LAT, T>(dd, n_inst, blocks, qb, mode, it, L);
+        case 1: return reduce_impl<1, LAT, T>(dd, n_inst, bmap, blocks, qb, mode, it, L);
+        case 2: return reduce_impl<2, LAT, T>(dd, n_inst, bmap, blocks, qb, mode, it, L);
+        case 3: return reduce_impl<3, LAT, T>(dd, n_inst, bmap, blocks, qb, mode, it, L);
+        case 4: return reduce_impl<4, LAT, T>(dd, n_inst, bmap, blocks, qb, mode, it, L);
+        default: return reduce_impl<kMaxP, LAT, T>(dd, n_inst, bmap, blocks, qb, mode, it, L);
     }
 }
 
 template <int T>
-static hipError_t reduce_dispatch_lat(const InstDesc* dd, int n_inst, int64_t blocks, int64_t qb, int p, int latent,
-                                      int mode, int it, const Launch& L) {
-    if (latent == 0) return reduce_dispatch_p<0, T>(dd, n_inst, blocks, qb, p, mode, it, L);
-    return reduce_dispatch_p<1, T>(dd, n_inst, blocks, qb, p, mode, it, L);
+static hipError_t reduce_dispatch_lat(const InstDesc* dd, int n_inst, const int32_t* bmap, int64_t blocks,
+                                      int64_t qb, int p, int latent, int mode, int it, const Launch& L) {
+    if (latent == 0) return reduce_dispatch_p<0, T>(dd, n_inst, bmap, blocks, qb, p, mode, it, L);
+    return reduce_dispatch_p<1, T>(dd, n_inst, bmap, blocks, qb, p, mode, it, L);
 }
 
 hipError_t launch_stress_units(const InstDesc* dd, int n_inst, int64_t count, int64_t q_base, int p, int latent, int T,
@@ -43,11 +47,12 @@ hipError_t launch_stress_units(const InstDesc* dd, int n_inst, int64_t count, in
 }
 
 hipError_t launch_stress_reduce(const InstDesc* dd, int n_inst, int64_t blocks, int64_t q_base, int p, int latent,
-                                int T, int mode, int it, hipStream_t s, LaunchTimer tm) {
-    const Launch L{s, tm};
-    if (T == 64) return reduce_dispatch_lat<64>(dd, n_inst, blocks, q_base, p, latent, mode, it, L);
-    if (T == 128) return reduce_dispatch_lat<128>(dd, n_inst, blocks, q_base, p, latent, mode, it, L);
-    return reduce_dispatch_lat<256>(dd, n_inst, blocks, q_base, p, latent, mode, it, L);
+                                int T, int mode, int it, int64_t max_n, hipStream_t s, LaunchTimer tm,
+                                const int32_t* bmap) {
+    const Launch L{s, tm, max_n <= kSmallReduceN};
+    if (T == 64) return reduce_dispatch_lat<64>(dd, n_inst, bmap, blocks, q_base, p, latent, mode, it, L);
+    if (T == 128) return reduce_dispatch_lat<128>(dd, n_inst, bmap, blocks, q_base, p, latent, mode, it, L);
+    return reduce_dispatch_lat<256>(dd, n_inst, bmap, blocks, q_base, p, latent, mode, it, L);
 }
 
 // Host mirror of reduce_blocks (must agree with the device functions above).

@@ -88,10 +88,12 @@ hipError_t launch_stress_units(const InstDesc* dd, int n_inst, int64_t count, in
                                bool grad, int loss, hipStream_t s, LaunchTimer tm = {});
 // Reduce the partials of every instance; `blocks` is the sum over instances
 // of reduce_block_count (instances sorted by red_off); blocks are numbered
-// from q_base.  StressMode says what
-// is produced; `it` indexes sigma_hist in descent mode.
+// from q_base; max_n is the largest n among them (it sizes the blocks);
+// bmap (device, optional) holds the instance of every block.
+// StressMode says what is produced; `it` indexes sigma_hist in descent mode.
 hipError_t launch_stress_reduce(const InstDesc* dd, int n_inst, int64_t blocks, int64_t q_base, int p, int latent,
-                                int T, int mode, int it, hipStream_t s, LaunchTimer tm = {});
+                                int T, int mode, int it, int64_t max_n, hipStream_t s, LaunchTimer tm = {},
+                                const int32_t* bmap = nullptr);
 int64_t reduce_block_count(int64_t n, int64_t nb, int T, int p);
 int units_per_tile(int T, int p);
 // One launch: all instances, all iterations of the descent.
@@ -113,18 +115,22 @@ hipError_t launch_sumsq(const float* Delta, int64_t n, int64_t ldd, int n_mat, i
                         float* out, int power, hipStream_t s);
 
 // Classical MDS (k_cmds.hip).  out = D^2 V over full rows of Delta (diagonal
-// skipped), V and out n x q row-major, q <= kMaxCmdsQ.
+// left out), V and out n x q row-major, q <= kMaxCmdsQ.
 hipError_t launch_d2v(const float* Delta, int64_t n, int64_t ldd, const float* V, int q, float* out, hipStream_t s);
-// out (qa*qb pairs (hi, lo)) = A^T B over n rows (B == nullptr: column sums of
-// A); `part` holds 2 * qa * qb * gram_blocks(n) floats.
-int64_t gram_blocks(int64_t n);
+// out (qa*qb (hi, lo) pairs) = A^T B over n rows (B == nullptr: column sums
+// of A, qb = 1); A2, B2, out2 (optional) a second product of the same shape
+// in the same launches.  `part` holds gram_part_floats() floats.
+int64_t gram_part_floats();
 hipError_t launch_gram(const float* A, int qa, const float* B, int qb, int64_t n, float* part, float* out,
-                       hipStream_t s);
-// out[i, :] = (alpha (A[i, :] - shift)) M; M qa x qb row-major (device),
-// shift (qa, device) may be null.
-// shift[c] = (sums[2c] + sums[2c+1]) / n, c < q <= 64 (column means from launch_gram's output).
-hipError_t launch_colmean(const float* sums, int q, int64_t n, float* shift, hipStream_t s);
-hipError_t launch_rowmat(const float* A, int qa, const float* shift, float alpha, const float* M, int qb, int64_t n,
+                       hipStream_t s, const float* A2 = nullptr, const float* B2 = nullptr, float* out2 = nullptr);
+// M (q x q, row-major) such that Y M has orthonormal columns, from the Gram
+// matrix g = Y^T Y (launch_gram's (hi, lo) output): Cholesky, then R^-1;
+// columns in the span of earlier ones become zero.
+hipError_t launch_chol_orth(const float* g, int q, float* M, hipStream_t s);
+// out[i, :] = (alpha (A[i, :] - mean)) M; M qa x qb row-major (device),
+// mean[c] = (sums[2c] + sums[2c+1]) / n from launch_gram's column sums of A
+// (sums may be null: no centring).
+hipError_t launch_rowmat(const float* A, int qa, const float* sums, float alpha, const float* M, int qb, int64_t n,
                          float* out, int64_t ldo, hipStream_t s);
 
 // Column standardisation (k_prep.hip): Y = (X - median) / sd per column

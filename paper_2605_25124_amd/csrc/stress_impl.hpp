@@ -557,7 +557,8 @@ __device__ __forceinline__ void stress_unit(const InstDesc& D, int64_t lu, float
 // Every sum below has a fixed shape that does not depend on how many threads
 // execute it, so the reduction launch (kRedWG threads) and the persistent
 // solver (kWG threads) produce bitwise identical results.
-constexpr int kRedWG = 1024;             // threads of a reduction block
+constexpr int kRedWG = 1024;             // threads of a reduction block for large instances
+constexpr int kRedWGSmall = 256;         // ... and when every instance of the launch is small
 constexpr int kNPT = 64;                 // points per reduction group (one per lane)
 constexpr int kVT = 1024;                // virtual threads of a stress slice
 
@@ -866,24 +867,32 @@ constexpr int reduce_lds_floats() {
 // offsets in red_off).  The first blocks of an instance sum one slice of its
 // stress each (with several slices, the last to finish adds them in order);
 // the following blocks take kNPT points each.
-template <int P, int LAT, int T>
-__global__ __launch_bounds__(kRedWG) void k_stress_reduce(const InstDesc* __restrict__ dd, int n_inst,
-                                                          int64_t q_base, int mode, int it) {
+template <int P, int LAT, int T, int NT>
+__global__ __launch_bounds__(NT) void k_stress_reduce(const InstDesc* __restrict__ dd, int n_inst,
+                                                      const int32_t* __restrict__ bmap, int64_t q_base, int mode,
+                                                      int it) {
     constexpr int PG = PG_<P, LAT>::value;
     __shared__ float lds[reduce_lds_floats<PG>()];
     __shared__ int last;
     const int64_t q = (int64_t)blockIdx.x + q_base;
-    int lo = 0, hi = n_inst - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (dd[mid].red_off <= q) lo = mid;
-        else hi = mid - 1;
+    // the instance of this block: from the host's block map when there is one
+    // (one load instead of a chain of dependent ones), else by binary search
+    int lo = 0;
+    if (bmap) {
+        lo = bmap[q];
+    } else {
+        int hi = n_inst - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (dd[mid].red_off <= q) lo = mid;
+            else hi = mid - 1;
+        }
     }
     const InstDesc& D = dd[lo];
     const int64_t b = q - D.red_off;
     const int ns = sigma_slices<T, P>(D);
     if (b < ns) {
-        const Comp part = sigma_slice<T, P, kRedWG>(D, (int)b, lds);
+        const Comp part = sigma_slice<T, P, NT>(D, (int)b, lds);
         if (threadIdx.x == 0) {
             if (ns == 1) {
                 write_sigma(D, mode, it, part);
@@ -911,7 +920,7 @@ __global__ __launch_bounds__(kRedWG) void k_stress_reduce(const InstDesc* __rest
         return;
     }
     if (mode == kModeSigma) return;
-    reduce_group<P, LAT, T, kRedWG>(D, (b - ns) * kNPT, mode, lds);
+    reduce_group<P, LAT, T, NT>(D, (b - ns) * kNPT, mode, lds);
 }
 
 // Persistent solver.  Queue item q = (iteration it, instance k, local unit),
@@ -1020,7 +1029,13 @@ static inline int p_bucket(int p) { return p <= 4 ? p : kMaxP; }
 struct Launch {
     hipStream_t s;
     LaunchTimer tm;
+    bool small = false;     // reduction launch: every instance has at most kSmallReduceN points
 };
+
+// Up to this many points per instance the reduction runs in blocks of
+// kRedWGSmall threads: the same fixed-shape sums, each thread taking several
+// of them, and a quarter of the waves.
+constexpr int64_t kSmallReduceN = 4096;
 
 template <typename K, typename... A>
 static hipError_t launch_k(K kernel, dim3 grid, dim3 block, const Launch& L, A... args) {
