@@ -29,6 +29,9 @@
  *   - Errors: arguments are validated on the host before any GPU work is
  *     enqueued; a failed check returns GINI_EINVAL (or GINI_EUNSUPPORTED) and
  *     enqueues nothing.  gini_last_error(ctx) then describes the failure.
+ *     Array arguments must be device memory of the context's GPU (or managed
+ *     memory): hipPointerGetAttributes is asked about each, and host memory
+ *     or a pointer HIP does not know is refused with GINI_EINVAL.
  *     A HIP runtime failure returns GINI_EDEVICE.
  *   - One context serves one host thread at a time.  Calls on two streams of
  *     one context share its scratch and must not overlap.
@@ -102,6 +105,11 @@ gini_status gini_weight_table(int32_t d, double nu, float* W);
  *     twoR[r*ldr + c] = 2*#{c' : V[r,c'] < V[r,c]} + #{c' : V[r,c'] == V[r,c]} + 1
  * V: rows x d FP32, leading dimension ldv >= d.  twoR: rows x d int32,
  * leading dimension ldr >= d.  rows == 0 is a no-op.  1 <= d <= 2^20.
+ * Rows of up to 256 coordinates are counted directly (O(d^2) compares, in
+ * LDS); longer rows are cut into chunks of 4096 that are sorted on the GPU,
+ * and every coordinate's counts come from binary searches in the sorted
+ * chunks (O(d log d) per pair of chunks).  The sorted chunks live in the
+ * context's scratch (at most 64 MiB; rows are processed in batches).
  * Bit-exact: integer result of FP32 comparisons.
  */
 gini_status gini_rank(gini_ctx* ctx, const float* V, int64_t rows, int32_t d, int64_t ldv,

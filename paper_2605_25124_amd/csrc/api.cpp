@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <numeric>
@@ -218,6 +219,41 @@ struct ProfScope {
         c->prof_ev[kind].emplace_back(a, b);
     }
 };
+
+// Every array argument must be memory a kernel on the context's GPU can use:
+// device memory of that GPU, or managed memory.  Host memory, or a pointer
+// HIP does not know, is refused here instead of faulting in a kernel.  Null
+// entries are skipped (optional arguments; required ones are checked before).
+gini_status check_dev(gini_ctx* c, std::initializer_list<std::pair<const void*, const char*>> ptrs) {
+    for (const auto& pr : ptrs) {
+        if (!pr.first) continue;
+        hipPointerAttribute_t a{};
+        const hipError_t e = hipPointerGetAttributes(&a, pr.first);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();               // leave no error behind for the next call
+            return fail(c, GINI_EINVAL, "%s is not memory allocated through HIP", pr.second);
+        }
+        if (a.type == hipMemoryTypeDevice) {
+            if (a.device != c->device)
+                return fail(c, GINI_EINVAL, "%s lives on device %d, the context on device %d", pr.second, a.device,
+                            c->device);
+        } else if (a.type != hipMemoryTypeManaged && a.type != hipMemoryTypeUnified) {
+            return fail(c, GINI_EINVAL, "%s is host memory: pass device memory", pr.second);
+        }
+    }
+    return GINI_OK;
+}
+
+gini_status check_dev_instances(gini_ctx* c, const gini_instance* inst, int32_t n_inst) {
+    for (int k = 0; k < n_inst; ++k) {
+        const gini_instance& I = inst[k];
+        gini_status st = check_dev(c, {{I.Delta, "Delta"}, {I.Z, "Z"}, {I.sigma_hist, "sigma_hist"},
+                                       {I.ks_hist, "ks_hist"}, {I.delta_sumsq, "delta_sumsq"},
+                                       {I.delta_sum, "delta_sum"}});
+        if (st != GINI_OK) return fail(c, st, "instance %d: %s", k, std::string(c->err).c_str());
+    }
+    return GINI_OK;
+}
 
 gini_status ensure_scratch(gini_ctx* c, size_t bytes) {
     if (bytes <= c->scratch_bytes) return GINI_OK;
@@ -483,6 +519,9 @@ gini_status stress_common(gini_ctx* c, const float* Delta, int64_t n, int64_t ld
                                        dsum);
     if (st != GINI_OK) return st;
     st = ensure_ready(c);
+    if (st != GINI_OK) return st;
+    st = check_dev(c, {{Delta, "Delta"}, {Z, "Z"}, {gradZ, "gradZ"}, {out_sigma, "out_sigma"}, {grad_out, "grad_out"},
+                       {dsum, "delta_sum"}});
     if (st != GINI_OK) return st;
     const int T = pick_tile(n);
     InstDesc D;
@@ -1010,7 +1049,15 @@ gini_status gini_rank(gini_ctx* c, const float* V, int64_t rows, int32_t d, int6
     if (rows == 0) return GINI_OK;
     gini_status st = ensure_ready(c);
     if (st != GINI_OK) return st;
-    GINI_HIP(c, gmds::launch_rank(V, rows, d, ldv, twoR, ldr, reinterpret_cast<hipStream_t>(stream)));
+    st = check_dev(c, {{V, "V"}, {twoR, "twoR"}});
+    if (st != GINI_OK) return st;
+    const int64_t words = gmds::rank_scratch_words(rows, d);
+    if (words > 0) {
+        st = ensure_scratch(c, (size_t)words * sizeof(uint32_t));
+        if (st != GINI_OK) return st;
+    }
+    GINI_HIP(c, gmds::launch_rank(V, rows, d, ldv, twoR, ldr, reinterpret_cast<uint32_t*>(c->scratch),
+                                  reinterpret_cast<hipStream_t>(stream)));
     return GINI_OK;
 }
 
@@ -1030,6 +1077,8 @@ gini_status gini_dissim(gini_ctx* c, const float* X, int64_t n, int32_t m, int64
         return fail(c, GINI_EINVAL, "stride_nu = %lld < n*ldd", (long long)stride_nu);
     if (n > (int64_t)1 << 22) return fail(c, GINI_EUNSUPPORTED, "n > 2^22 is not supported");
     gini_status st = ensure_ready(c);
+    if (st != GINI_OK) return st;
+    st = check_dev(c, {{X, "X"}, {Delta, "Delta"}});
     if (st != GINI_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     float* w = nullptr;
@@ -1063,6 +1112,8 @@ static gini_status sum_common(gini_ctx* c, const float* Delta, int64_t n, int64_
     if (n > (int64_t)1 << 31) return fail(c, GINI_EUNSUPPORTED, "n too large");
     gini_status st = ensure_ready(c);
     if (st != GINI_OK) return st;
+    st = check_dev(c, {{Delta, "Delta"}, {out, "out"}});
+    if (st != GINI_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     st = ensure_scratch(c, (size_t)2 * n_mat * std::max<int64_t>(1, gmds::sumsq_blocks(n)) * sizeof(float));
     if (st != GINI_OK) return st;
@@ -1091,6 +1142,8 @@ gini_status gini_sammon_step(gini_ctx* c, const float* Delta, int64_t n, int64_t
     if (st != GINI_OK) return st;
     if (n > (int64_t)1 << 31) return fail(c, GINI_EUNSUPPORTED, "n too large");
     st = ensure_ready(c);
+    if (st != GINI_OK) return st;
+    st = check_dev(c, {{Delta, "Delta"}});
     if (st != GINI_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     // scratch: [sum hi, lo][max row sum][pad][sum partials][row-max partials]
@@ -1148,6 +1201,8 @@ gini_status gini_stress_bwd_static(gini_ctx* c, const float* Delta, int64_t n, i
     unsigned char* base = nullptr;
     st = static_scratch(c, &base);
     if (st != GINI_OK) return st;
+    st = check_dev(c, {{Delta, "Delta"}, {Z, "Z"}, {gradZ, "gradZ"}, {out_sigma, "out_sigma"}, {grad_out, "grad_out"}});
+    if (st != GINI_OK) return st;
     assign_partials(D, reinterpret_cast<float*>(base + kStaticHead), T, pg);
     D.instcnt = reinterpret_cast<uint32_t*>(base + kStaticCounter);
     InstDesc* dd = reinterpret_cast<InstDesc*>(base);
@@ -1182,6 +1237,8 @@ gini_status gini_mds_solve(gini_ctx* c, const gini_instance* inst, int32_t n_ins
     st = validate_instances(c, inst, n_inst);
     if (st != GINI_OK) return st;
     st = ensure_ready(c);
+    if (st != GINI_OK) return st;
+    st = check_dev_instances(c, inst, n_inst);
     if (st != GINI_OK) return st;
     return solve_impl(c, inst, n_inst, opts, reinterpret_cast<hipStream_t>(stream));
 }
@@ -1236,6 +1293,8 @@ gini_status gini_autotune(gini_ctx* c, const gini_instance* inst, int32_t n_inst
     gini_status st = validate_instances(c, inst, n_inst);
     if (st != GINI_OK) return st;
     st = ensure_ready(c);
+    if (st != GINI_OK) return st;
+    st = check_dev_instances(c, inst, n_inst);
     if (st != GINI_OK) return st;
     const int keep = best->flags & GINI_SOLVE_CHECK_FINITE;
     st = autotune_impl(c, inst, n_inst, probe_iters, best, reinterpret_cast<hipStream_t>(stream));
@@ -1298,6 +1357,8 @@ gini_status gini_select_nu(gini_ctx* c, const float* X, int64_t n, int32_t m, in
     st = check_opts(c, &so);
     if (st != GINI_OK) return st;
     st = ensure_ready(c);
+    if (st != GINI_OK) return st;
+    st = check_dev(c, {{X, "X"}, {Z0, "Z0"}, {Z_out, "Z_out"}});
     if (st != GINI_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
@@ -1414,6 +1475,8 @@ gini_status gini_alternate_nu(gini_ctx* c, const float* X, int64_t n, int32_t m,
     if (st != GINI_OK) return st;
     st = ensure_ready(c);
     if (st != GINI_OK) return st;
+    st = check_dev(c, {{X, "X"}, {Z0, "Z0"}, {Z_out, "Z_out"}});
+    if (st != GINI_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
     // workspace: the n_nu matrices, then per nu (sum, sum of squares, Euclidean stress) as (hi, lo)
@@ -1514,6 +1577,8 @@ gini_status gini_classical_mds(gini_ctx* c, const float* Delta, int64_t n, int64
     if (!(tol >= 0.0)) return fail(c, GINI_EINVAL, "tol must be >= 0");
     if (n > (int64_t)1 << 31) return fail(c, GINI_EUNSUPPORTED, "n too large");
     gini_status st = ensure_ready(c);
+    if (st != GINI_OK) return st;
+    st = check_dev(c, {{Delta, "Delta"}, {Z, "Z"}});
     if (st != GINI_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int q = (int)std::min<int64_t>({(int64_t)gmds::kMaxCmdsQ, (int64_t)p + 4, n - 1});
@@ -1665,6 +1730,8 @@ gini_status gini_standardize(gini_ctx* c, const float* X, int64_t n, int32_t m, 
     if (n > ((int64_t)1 << 32) - 1) return fail(c, GINI_EUNSUPPORTED, "n too large");
     if (m > 65535) return fail(c, GINI_EUNSUPPORTED, "m > 65535 is not supported");
     gini_status st = ensure_ready(c);
+    if (st != GINI_OK) return st;
+    st = check_dev(c, {{X, "X"}, {Y, "Y"}, {stats, "stats"}});
     if (st != GINI_OK) return st;
     GINI_HIP(c, gmds::launch_standardise(X, n, m, ldx, Y, ldy, stats, reinterpret_cast<hipStream_t>(stream)));
     return GINI_OK;

@@ -77,7 +77,10 @@ struct DissimArgs {
 };
 
 // ---- launchers (return hipSuccess or the launch error) ----
-hipError_t launch_rank(const float* V, int64_t rows, int d, int64_t ldv, int32_t* t, int64_t ldr,
+// scratch: rank_scratch_words(rows, d) words (device; the sorted chunks of
+// rows longer than 256).
+int64_t rank_scratch_words(int64_t rows, int d);
+hipError_t launch_rank(const float* V, int64_t rows, int d, int64_t ldv, int32_t* t, int64_t ldr, uint32_t* scratch,
                        hipStream_t s);
 
 hipError_t launch_dissim(const DissimArgs& a, hipStream_t s);

@@ -27,14 +27,24 @@ def _rows(kind, rows, d, seed):
     return synth.signed_zero_rows(g, rows, d)
 
 
-@pytest.mark.parametrize("d", [1, 2, 3, 4, 10, 16, 63, 64, 65, 255, 256, 257, 784, 1000, 4097])
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 10, 16, 63, 64, 65, 255, 256, 257, 784, 1000, 4095, 4096, 4097, 8193,
+                               40000])
 @pytest.mark.parametrize("kind", ["gauss", "ties", "const", "zeros"])
 def test_rank_bit_exact(gm, orc, d, kind):
-    rows = 37 if d < 1000 else 5
+    rows = 37 if d < 1000 else (5 if d < 10000 else 2)
     V = _rows(kind, rows, d, 1000 + d)
     t = gm.gini_rank(torch.from_numpy(V).to(DEV)).cpu().numpy()
     ref = orc.rank2_rows(V)
     assert np.array_equal(t, ref)
+
+
+def test_rank_rows_in_batches(gm, orc):
+    """Long rows are ranked through sorted chunks in a bounded scratch: more
+    rows than one batch holds (2^24 words) are processed batch by batch."""
+    rows, d = 3400, 5000
+    V = _rows("ties", rows, d, 77)
+    t = gm.gini_rank(torch.from_numpy(V).to(DEV)).cpu().numpy()
+    assert np.array_equal(t, orc.rank2_rows(V))
 
 
 def test_rank_strided_and_empty(gm, orc):
