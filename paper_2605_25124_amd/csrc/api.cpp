@@ -1095,6 +1095,9 @@ gini_status gini_dissim(gini_ctx* c, const float* X, int64_t n, int32_t m, int64
     a.m = m;
     a.n_nu = n_nu;
     a.half_m = 0.5f * (float)m;
+    a.lin = 1;
+    for (int k = 0; k < n_nu; ++k) a.lin = a.lin && nu[k] == 2.0;
+    a.vecx = (aligned16(X) && (ldx % 4) == 0) ? 1 : 0;
     ProfScope ps(c, kProfDissim, s);
     GINI_HIP(c, gmds::launch_dissim(a, s));
     return GINI_OK;

@@ -150,7 +150,7 @@ __device__ void write_tile(const DissimArgs& A, int nu0, int nq, const float* ou
 // ------------------------------------------------------- lane per pair
 // B is a size bucket (compile time), m <= B the runtime length; positions
 // m..B-1 hold +inf, which the all-ascending network never moves.
-template <int B>
+template <int B, bool LIN>
 __global__ __launch_bounds__(kDWG) void k_dissim_lane(DissimArgs A, int nu0, int nq) {
     constexpr int TS = 32;
     __shared__ float xs[2 * TS * 65];
@@ -194,10 +194,12 @@ __global__ __launch_bounds__(kDWG) void k_dissim_lane(DissimArgs A, int nu0, int
         });
         sort_lane<B>(v);
         bool tie = false;
-        static_for<B - 1>([&](auto kc) {
-            constexpr int k = decltype(kc)::value + 1;
-            tie = tie || ((k < m) && (v[k] == v[k - 1]));
-        });
+        if constexpr (!LIN) {
+            static_for<B - 1>([&](auto kc) {
+                constexpr int k = decltype(kc)::value + 1;
+                tie = tie || ((k < m) && (v[k] == v[k - 1]));
+            });
+        }
         // untied positions: t = 2k + 2, weight index 2k, the same for every lane
         // (scalar loads; one nu at a time keeps them within the SGPR budget)
 #pragma unroll 1
@@ -213,7 +215,7 @@ __global__ __launch_bounds__(kDWG) void k_dissim_lane(DissimArgs A, int nu0, int
                 o[q * TS * (TS + 1)] = A.half_m * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
             }
         }
-        if (__any(tie)) {
+        if (!LIN && __any(tie)) {
             if (tie) {
                 // With ties the lane recomputes the sum run by run: a run a..b
                 // of equal values z contributes (b-a+1) z W[a+b+2].
@@ -325,7 +327,7 @@ __device__ __forceinline__ int wskew(int ti) {
 template <int G, int E>
 constexpr int dissim_group_waves() { return (G == 32 && E == 32) ? 5 : 1; }
 
-template <int G, int E>
+template <int G, int E, bool LIN>
 __global__ __launch_bounds__(kDWG) __attribute__((amdgpu_waves_per_eu(dissim_group_waves<G, E>())))
 void k_dissim_group(DissimArgs A, int nu0, int nq) {
     constexpr int TS = 16;
@@ -367,18 +369,49 @@ void k_dissim_group(DissimArgs A, int nu0, int nq) {
         float v[E];
         const float* xi = A.X + i * A.ldx;
         const float* xj = A.X + j * A.ldx;
-        static_for<E>([&](auto rc) {
-            constexpr int rr = decltype(rc)::value;
-            const int cc = rr * G + g;
-            v[rr] = (cc < m) ? (xi[cc] - xj[cc]) : inf;
-        });
+        if (A.vecx) {
+            // lane g takes the coordinates g*E .. g*E+E-1 in 16-byte loads
+            // (which value starts at which position does not matter: they
+            // are sorted next)
+            const int c0 = g * E;
+            static_for<E / 4>([&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                const int cc = c0 + 4 * q;
+                if (cc + 3 < m) {
+                    const float4 a = *reinterpret_cast<const float4*>(xi + cc);
+                    const float4 b = *reinterpret_cast<const float4*>(xj + cc);
+                    v[4 * q] = a.x - b.x;
+                    v[4 * q + 1] = a.y - b.y;
+                    v[4 * q + 2] = a.z - b.z;
+                    v[4 * q + 3] = a.w - b.w;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[4 * q + e] = (cc + e < m) ? (xi[cc + e] - xj[cc + e]) : inf;
+                }
+            });
+        } else {
+            static_for<E>([&](auto rc) {
+                constexpr int rr = decltype(rc)::value;
+                const int cc = rr * G + g;
+                v[rr] = (cc < m) ? (xi[cc] - xj[cc]) : inf;
+            });
+        }
         bitonic_blocked<G, E>(v, g);
-        // run starts (forward)
         const int e0 = g * E;
+        int a[E];
+        if constexpr (LIN) {
+            // weights linear in t: a run of ties gets the same total weight
+            // with every element at its own sorted position (t = 2e + 2) as
+            // with all of them at the run's midrank, so no run is needed
+            static_for<E>([&](auto rc) {
+                constexpr int rr = decltype(rc)::value;
+                a[rr] = (e0 + rr < m) ? wskew<E>(2 * (e0 + rr)) : -1;
+            });
+        } else {
+        // run starts (forward)
         const float prevv = __shfl_up(v[E - 1], 1, G);
         const float nextv = __shfl_down(v[0], 1, G);
         // a[rr]: start of the run holding element e0+rr (-1: begins in an earlier lane)
-        int a[E];
         int run = -1;
         int first_end = 0x7fffffff;
         static_for<E>([&](auto rc) {
@@ -406,6 +439,7 @@ void k_dissim_group(DissimArgs A, int nu0, int nq) {
             const int ti = min(max(aa + bcur, 0), 2 * m - 2);
             a[rr] = (e0 + rr < m) ? wskew<E>(ti) : -1;
         });
+        }
         for (int q = 0; q < nq; ++q) {
             const float* wq = wt + q * wstride;
             float s0 = 0.f, s1 = 0.f;
@@ -428,7 +462,8 @@ void k_dissim_group(DissimArgs A, int nu0, int nq) {
 template <int B>
 static hipError_t lane_impl(const DissimArgs& a, int nu0, int nq, hipStream_t s) {
     const int64_t nb = (a.n + 31) / 32;
-    hipLaunchKernelGGL(k_dissim_lane<B>, dim3((unsigned)tri_count(nb)), dim3(kDWG), 0, s, a, nu0, nq);
+    if (a.lin) hipLaunchKernelGGL((k_dissim_lane<B, true>), dim3((unsigned)tri_count(nb)), dim3(kDWG), 0, s, a, nu0, nq);
+    else hipLaunchKernelGGL((k_dissim_lane<B, false>), dim3((unsigned)tri_count(nb)), dim3(kDWG), 0, s, a, nu0, nq);
     return hipGetLastError();
 }
 
@@ -450,7 +485,10 @@ static hipError_t group_impl(const DissimArgs& a, int nu0, int nq, hipStream_t s
     const int wlen = 2 * a.m - 1;
     const int wstride = wlen + wlen / (2 * E) + 1;
     const size_t shm = sizeof(float) * ((size_t)nq * wstride + (size_t)nq * 16 * 17);
-    hipLaunchKernelGGL((k_dissim_group<G, E>), dim3((unsigned)tri_count(nb)), dim3(kDWG), shm, s, a, nu0, nq);
+    if (a.lin) hipLaunchKernelGGL((k_dissim_group<G, E, true>), dim3((unsigned)tri_count(nb)), dim3(kDWG), shm, s, a, nu0,
+                                  nq);
+    else hipLaunchKernelGGL((k_dissim_group<G, E, false>), dim3((unsigned)tri_count(nb)), dim3(kDWG), shm, s, a, nu0,
+                            nq);
     return hipGetLastError();
 }
 

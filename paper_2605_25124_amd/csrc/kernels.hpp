@@ -74,6 +74,8 @@ struct DissimArgs {
     int64_t n, ldx, ldd, stride_nu;
     int32_t m, n_nu;
     float half_m;          // m / 2
+    int32_t lin;           // every nu of the call is 2: the weights are linear in t (ties need no runs)
+    int32_t vecx;          // X rows start on 16 bytes (16-byte loads)
 };
 
 // ---- launchers (return hipSuccess or the launch error) ----
