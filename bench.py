@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--n", type=int, default=10000)
     ap.add_argument("--sweep-iters", type=int, default=200)
     ap.add_argument("--plain-iters", type=int, default=40)
+    ap.add_argument("--persistent-iters", type=int, default=10)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-select", action="store_true")
@@ -60,7 +61,7 @@ def parse():
                     help="latent dimensions of the heavy workload (default 3; 2 measures the pure-HBM p = 2 case)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the Sammon-loss and classical-MDS measurements on the image workload")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=5.0)
     ap.add_argument("--mode", choices=["auto", "persistent", "batched"], default="auto")
     ap.add_argument("--tile", type=int, default=256)
     ap.add_argument("--sweep-mode", choices=["auto", "persistent", "batched"], default="auto")
@@ -121,9 +122,10 @@ def cpu_leg(args, w, D, Z0, nu, p, gm, dev):
     import numpy as np
     import torch
     from oracle import oracle as O
+    from paper_2605_25124_amd import synth
 
     n, m = w.X.shape
-    ns = 400 if m > 128 else 700
+    ns = 700
     old_aff = os.sched_getaffinity(0)
     core = min(old_aff)
     os.sched_setaffinity(0, {core})
@@ -137,9 +139,15 @@ def cpu_leg(args, w, D, Z0, nu, p, gm, dev):
         while True:
             Zs, _ = O.solve(Dso, Zs, nu, 1, O.LATENT_GINI, O.MATCH32)   # stress + gradient + step
             reps += 1
-            if time.perf_counter() - t0 >= args.cpu_seconds:
+            if reps >= 10 and time.perf_counter() - t0 >= args.cpu_seconds:
                 break
         t_steps = time.perf_counter() - t0
+        # the small workload in full: Delta of 200 x 10 rows and 100 descent steps
+        ws = synth.workload_small()
+        t0 = time.perf_counter()
+        Dsm = O.dissim(ws.X, [2.0], O.MATCH32)[0]
+        O.solve(Dsm, ws.Z0[0].astype(np.float64), 2.0, ws.iters, O.LATENT_GINI, O.MATCH32)
+        t_small = time.perf_counter() - t0
     finally:
         os.sched_setaffinity(0, old_aff)
     sp = ns * (ns - 1) // 2
@@ -148,8 +156,10 @@ def cpu_leg(args, w, D, Z0, nu, p, gm, dev):
     cpu = {"value": round(step_rate, 1), "unit": "pair-evals/s", "cores": 1, "kind": "oracle",
            "sample": f"FP64 oracle, one thread pinned to one core: Gini Delta of the first {ns} rows of the "
                      f"workload ({sp} pairs, m={m}) in {t_delta:.2f} s, then {reps} descent steps on it (stress + "
-                     f"gradient + update, p={p} Gini latent) in {t_steps:.1f} s",
+                     f"gradient + update, p={p} Gini latent) in {t_steps:.1f} s; small_workload_full_s: Delta of "
+                     f"the 200 x 10 workload and its 100 descent steps",
            "dissim_pairs_per_s": round(sp / t_delta, 1),
+           "small_workload_full_s": round(t_small, 3),
            "extrapolated_n2": {"note": f"n^2 extrapolation from the {ns}-row sample to n={n}, not measured",
                                "dissim_build_s": round(t_delta * full / sp, 1),
                                "descent_step_s": round(full / step_rate, 3)},
@@ -301,6 +311,9 @@ def main():
             "kernel": kname,
             "avg_launch_us": round(avg_ms * 1e3, 2), "alg_bytes_per_launch": alg_bytes,
             "reduce_avg_us": round(prof["reduce_ms"] * 1e3 / max(prof["reduce_launches"], 1), 2)}
+    if kname == "k_stress_units":
+        # the step without the per-call fixed cost and launch gaps: its two kernels
+        roof["step_kernels_us"] = round(roof["avg_launch_us"] + roof["reduce_avg_us"], 2)
     log(f"roofline {kname}: {avg_ms * 1e3:.1f} us/launch -> {achieved:.0f} GB/s")
 
     # ---- the Sammon loss and classical MDS on the same Delta (n = 10^4)
@@ -395,10 +408,22 @@ def main():
         torch.cuda.synchronize()
         tp = time.perf_counter() - t0
         plain_rate = n_inst * args.plain_iters / tp
+        # the persistent single-launch mode, few iterations (it pays one
+        # device-scope release per work unit)
+        I3 = insts()
+        gm.gini_mds_solve(I3, 1, gm.SOLVE_PERSISTENT, tuned["tile"])
+        I3 = insts()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gm.gini_mds_solve(I3, args.persistent_iters, gm.SOLVE_PERSISTENT, tuned["tile"])
+        torch.cuda.synchronize()
+        persistent_rate = n_inst * args.persistent_iters / (time.perf_counter() - t0)
         sweep = {"workload": "16 Gaussian-mixture problems n~U{100..3000} m~U{4..64} x 8 nu in [1.1,4], p=2",
                  "instances": n_inst, "batched_mode": "persistent" if tuned["flags"] == gm.SOLVE_PERSISTENT
                  else "batched", "tile": tuned["tile"], "grid": tuned["grid"],
                  "batched_iters_per_s": round(batched_rate, 1), "plain_iters_per_s": round(plain_rate, 1),
+                 "persistent_iters_per_s": round(persistent_rate, 1),
+                 "sweep_iteration_us": round(1e6 * n_inst / batched_rate, 1),
                  "speedup": round(batched_rate / plain_rate, 2), "batched_iters": args.sweep_iters,
                  "plain_iters": args.plain_iters, "dissim_build_s": round(sweep_build, 3)}
         log(f"sweep batched {batched_rate:.0f} it/s, plain {plain_rate:.0f} it/s, x{batched_rate / plain_rate:.2f}")
