@@ -399,6 +399,17 @@ def main():
         torch.cuda.synchronize()
         tb = time.perf_counter() - t0
         batched_rate = n_inst * args.sweep_iters / tb
+        # per-kernel times of the same iterations (HIP events around every launch)
+        sweep_kernels = None
+        if tuned["flags"] == gm.SOLVE_BATCHED:
+            I1 = insts()
+            gm.gini_profile_enable(0, True)
+            gm.gini_mds_solve(I1, 20, tuned["flags"], tuned["tile"], tuned["grid"])
+            torch.cuda.synchronize()
+            pr_s = gm.gini_profile_read(0)
+            gm.gini_profile_enable(0, False)
+            sweep_kernels = {"units_us": round(pr_s["tile_ms"] * 1e3 / max(pr_s["tile_launches"], 1), 2),
+                             "reduce_us": round(pr_s["reduce_ms"] * 1e3 / max(pr_s["reduce_launches"], 1), 2)}
         I2 = insts()
         gm.gini_mds_solve(I2, 2, gm.SOLVE_PLAIN, tuned["tile"])
         I2 = insts()
@@ -424,6 +435,7 @@ def main():
                  "batched_iters_per_s": round(batched_rate, 1), "plain_iters_per_s": round(plain_rate, 1),
                  "persistent_iters_per_s": round(persistent_rate, 1),
                  "sweep_iteration_us": round(1e6 * n_inst / batched_rate, 1),
+                 "sweep_iteration_kernels": sweep_kernels,
                  "speedup": round(batched_rate / plain_rate, 2), "batched_iters": args.sweep_iters,
                  "plain_iters": args.plain_iters, "dissim_build_s": round(sweep_build, 3)}
         log(f"sweep batched {batched_rate:.0f} it/s, plain {plain_rate:.0f} it/s, x{batched_rate / plain_rate:.2f}")
