@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=5.0)
     ap.add_argument("--mode", choices=["auto", "persistent", "batched"], default="auto")
     ap.add_argument("--tile", type=int, default=256)
-    ap.add_argument("--sweep-mode", choices=["auto", "persistent", "batched"], default="auto")
+    ap.add_argument("--sweep-mode", choices=["auto", "persistent", "batched", "split"], default="auto")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run a plain device copy of 256 MiB (calibration of memory counters)")
     ap.add_argument("--sweep-tile", type=int, default=0)
@@ -387,7 +387,8 @@ def main():
         if args.sweep_mode == "auto":
             tuned = gm.gini_autotune(insts(), 20)
         else:
-            tuned = {"flags": gm.SOLVE_PERSISTENT if args.sweep_mode == "persistent" else gm.SOLVE_BATCHED,
+            tuned = {"flags": {"persistent": gm.SOLVE_PERSISTENT, "batched": gm.SOLVE_BATCHED,
+                               "split": gm.SOLVE_BATCHED | gm.SOLVE_SPLIT}[args.sweep_mode],
                      "tile": args.sweep_tile or 64, "grid": 0}
         log(f"sweep: {n_inst} instances, build {sweep_build:.2f} s, tuned {tuned}")
         I1 = insts()
@@ -401,7 +402,7 @@ def main():
         batched_rate = n_inst * args.sweep_iters / tb
         # per-kernel times of the same iterations (HIP events around every launch)
         sweep_kernels = None
-        if tuned["flags"] == gm.SOLVE_BATCHED:
+        if tuned["flags"] & gm.SOLVE_BATCHED:
             I1 = insts()
             gm.gini_profile_enable(0, True)
             gm.gini_mds_solve(I1, 20, tuned["flags"], tuned["tile"], tuned["grid"])
@@ -431,7 +432,8 @@ def main():
         persistent_rate = n_inst * args.persistent_iters / (time.perf_counter() - t0)
         sweep = {"workload": "16 Gaussian-mixture problems n~U{100..3000} m~U{4..64} x 8 nu in [1.1,4], p=2",
                  "instances": n_inst, "batched_mode": "persistent" if tuned["flags"] == gm.SOLVE_PERSISTENT
-                 else "batched", "tile": tuned["tile"], "grid": tuned["grid"],
+                 else ("batched, two streams" if tuned["flags"] & gm.SOLVE_SPLIT else "batched"),
+                 "tile": tuned["tile"], "grid": tuned["grid"],
                  "batched_iters_per_s": round(batched_rate, 1), "plain_iters_per_s": round(plain_rate, 1),
                  "persistent_iters_per_s": round(persistent_rate, 1),
                  "sweep_iteration_us": round(1e6 * n_inst / batched_rate, 1),

@@ -272,13 +272,14 @@ enum {
     GINI_SOLVE_PLAIN = 2,        /* per instance, per iteration: 2 launches     */
     GINI_SOLVE_BATCHED = 4,      /* per iteration: 2 launches for all instances */
     GINI_SOLVE_AUTOTUNE = 8,     /* choose tile, grid and mode by measurement   */
-    GINI_SOLVE_CHECK_FINITE = 16 /* return GINI_ENOTFINITE if a sigma is not    */
+    GINI_SOLVE_CHECK_FINITE = 16, /* return GINI_ENOTFINITE if a sigma is not   */
+    GINI_SOLVE_SPLIT = 32        /* with BATCHED: two groups on two streams     */
 };
 
 typedef struct {
     int32_t iters;     /* >= 0                                                  */
     int32_t flags;     /* one of PERSISTENT / PLAIN / BATCHED, or AUTOTUNE;
-                          plus CHECK_FINITE                                     */
+                          plus CHECK_FINITE; SPLIT only together with BATCHED   */
     int32_t tile;      /* 0 = library choice, else 64, 128 or 256               */
     int32_t grid;      /* persistent workgroups; 0 = library choice             */
 } gini_solve_opts;
@@ -294,8 +295,13 @@ typedef struct {
  * must not share Z, sigma_hist or ks_hist; an instance with ks_hist needs
  * delta_sumsq, and ks_hist[t] = sqrt(sigma_hist[t] / (delta_sumsq[0] +
  * delta_sumsq[1])) is formed in FP64 from the compensated sigma (0 when the
- * normaliser is 0).  The three modes give bitwise identical
- * results for the same tile size.  Synchronises `stream` before returning
+ * normaliser is 0).  BATCHED | SPLIT deals the instances (largest first) into
+ * two groups of about equal work and issues each group's launches on its own
+ * stream (`stream`, and a stream the context owns, joined to `stream` before
+ * the call returns), so that the reduction of one group runs beside the
+ * stress units of the other; with one instance it is plain BATCHED.  All
+ * modes give bitwise identical results for the same tile size (every
+ * instance's sums have a fixed shape).  Synchronises `stream` before returning
  * (to report device-side failures); a persistent launch that stops making
  * progress aborts and returns GINI_EDEVICE.
  */
@@ -307,10 +313,11 @@ gini_status gini_mds_solve(gini_ctx* ctx, const gini_instance* inst, int32_t n_i
  * instances over `probe_iters` iterations each, on copies of the
  * configurations (the caller's Z and histories are not modified), and write
  * the fastest into *best (flags keep the caller's CHECK_FINITE bit).  The
- * candidates are the batched mode at every tile size, and the persistent mode
- * at several grid sizes only where one iteration has no more work units than
- * the GPU has compute units (elsewhere its per-unit release costs more than
- * two launches per iteration).  The
+ * candidates are the batched mode at every tile size (with and without
+ * SPLIT when there are several instances), and the persistent mode at several
+ * grid sizes only where one iteration has no more work units than the GPU has
+ * compute units (elsewhere its per-unit release costs more than two launches
+ * per iteration).  The
  * result is cached in the context, keyed by the batch's shape, and used by
  * gini_mds_solve with GINI_SOLVE_AUTOTUNE.  Synchronises `stream`.
  */

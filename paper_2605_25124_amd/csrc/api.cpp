@@ -56,6 +56,9 @@ struct TuneEntry {
 
 }  // namespace
 
+// Streams (groups of instances) of a split batched solve.
+constexpr int kSplitGroups = 2;
+
 struct gini_ctx {
     int device = 0;
     bool ready = false;
@@ -90,6 +93,9 @@ struct gini_ctx {
     hipEvent_t cm_ev[4] = {};
     hipEvent_t cm_ready[4] = {};
     hipStream_t cm_copy = nullptr;   // the copies to the landing slots run beside the iteration
+    // the extra streams of a split batched solve, and the fork / join events
+    hipStream_t side[kSplitGroups - 1] = {};
+    hipEvent_t side_fork = nullptr, side_join[kSplitGroups - 1] = {};
 };
 
 namespace {
@@ -675,11 +681,109 @@ __global__ void k_reset_ctl(gmds::SolveCtl* ctl, uint32_t* ep, int n) {
     if (i < n) ep[i] = 0u;
 }
 
+gini_status ensure_side(gini_ctx* c) {
+    if (c->side_fork) return GINI_OK;
+    for (int g = 0; g < kSplitGroups - 1; ++g) {
+        GINI_HIP(c, hipEventCreateWithFlags(&c->side_join[g], hipEventDisableTiming));
+        GINI_HIP(c, hipStreamCreateWithFlags(&c->side[g], hipStreamNonBlocking));
+    }
+    GINI_HIP(c, hipEventCreateWithFlags(&c->side_fork, hipEventDisableTiming));
+    return GINI_OK;
+}
+
+// Batched descent in kSplitGroups groups of instances, one stream each.
+// Instances are dealt largest first to the group with the least work so far
+// (work = stress units per iteration); each group gets descriptors with its
+// own unit and reduction-block numbering, and its launches alternate with the
+// other groups' on the host, so that the GPU runs one group's reduction beside
+// the others' stress units.  An instance's partials, counters and sums are
+// those of the one-group launch, so the results are bitwise the same.
+gini_status run_split(gini_ctx* c, Plan& P, int iters, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    constexpr int NG = kSplitGroups;
+    const int n_inst = (int)P.desc.size();
+    const int ng = std::min(NG, n_inst);
+    struct Group {
+        std::vector<InstDesc> desc;
+        std::vector<int32_t> bmap;
+        int64_t tiles = 0, rblocks = 0, maxn = 0;
+    } G[NG];
+    for (int k = 0; k < n_inst; ++k) {
+        int gi = 0;
+        for (int g = 1; g < ng; ++g)
+            if (G[g].tiles < G[gi].tiles) gi = g;
+        Group& g = G[gi];
+        InstDesc d = P.desc[k];
+        const int64_t units = P.prefix[k + 1] - P.prefix[k];
+        const int64_t rb = (k + 1 < n_inst ? P.desc[k + 1].red_off : P.rblocks) - P.desc[k].red_off;
+        d.tile_off = g.tiles;
+        d.red_off = g.rblocks;
+        g.bmap.insert(g.bmap.end(), (size_t)rb, (int32_t)g.desc.size());
+        g.desc.push_back(d);
+        g.tiles += units;
+        g.rblocks += rb;
+        g.maxn = std::max(g.maxn, d.n);
+    }
+    // one upload: the descriptor arrays, then the block maps
+    size_t off[2 * NG];
+    size_t bytes = 0;
+    for (int g = 0; g < ng; ++g) {
+        off[g] = bytes;
+        bytes = (bytes + G[g].desc.size() * sizeof(InstDesc) + 15) & ~size_t(15);
+    }
+    for (int g = 0; g < ng; ++g) {
+        off[NG + g] = bytes;
+        bytes += G[g].bmap.size() * sizeof(int32_t);
+    }
+    std::vector<unsigned char> blob(bytes);
+    for (int g = 0; g < ng; ++g) {
+        std::memcpy(blob.data() + off[g], G[g].desc.data(), G[g].desc.size() * sizeof(InstDesc));
+        std::memcpy(blob.data() + off[NG + g], G[g].bmap.data(), G[g].bmap.size() * sizeof(int32_t));
+    }
+    gini_status st = ensure_side(c);
+    if (st != GINI_OK) return st;
+    void* dd = nullptr;
+    Slot* sl = nullptr;
+    st = upload(c, blob.data(), blob.size(), s, &dd, &sl);
+    if (st != GINI_OK) return st;
+    auto at = [&](size_t o) { return static_cast<unsigned char*>(dd) + o; };
+    hipStream_t str[NG];
+    str[0] = s;
+    for (int g = 1; g < NG; ++g) str[g] = c->side[g - 1];
+    if (ev0) GINI_HIP(c, hipEventRecord(ev0, s));
+    GINI_HIP(c, hipEventRecord(c->side_fork, s));
+    for (int g = 1; g < ng; ++g) GINI_HIP(c, hipStreamWaitEvent(str[g], c->side_fork, 0));
+    for (int it = 0; it < iters; ++it) {
+        for (int g = 0; g < ng; ++g) {
+            const InstDesc* ddp = reinterpret_cast<const InstDesc*>(at(off[g]));
+            const int32_t* bmap = reinterpret_cast<const int32_t*>(at(off[NG + g]));
+            const int ni = (int)G[g].desc.size();
+            {
+                ProfScope ps(c, kProfTile, str[g], true);
+                GINI_HIP(c, gmds::launch_stress_units(ddp, ni, G[g].tiles, 0, P.p, P.latent, P.T, true, P.loss,
+                                                      str[g], ps.timer()));
+            }
+            ProfScope ps(c, kProfReduce, str[g], true);
+            GINI_HIP(c, gmds::launch_stress_reduce(ddp, ni, G[g].rblocks, 0, P.p, P.latent, P.T, gmds::kModeDescent,
+                                                   it, G[g].maxn, str[g], ps.timer(), bmap));
+        }
+    }
+    for (int g = 1; g < ng; ++g) {
+        GINI_HIP(c, hipEventRecord(c->side_join[g - 1], str[g]));
+        GINI_HIP(c, hipStreamWaitEvent(s, c->side_join[g - 1], 0));
+    }
+    if (ev1) GINI_HIP(c, hipEventRecord(ev1, s));
+    st = slot_done(c, sl, s);
+    if (st != GINI_OK) return st;
+    GINI_HIP(c, hipStreamSynchronize(s));
+    return GINI_OK;
+}
+
 // ev0/ev1 (optional) are recorded right before the first and after the last
 // kernel launch, so that their interval holds only the solve's GPU work.
 gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStream_t s, hipEvent_t ev0 = nullptr,
-                     hipEvent_t ev1 = nullptr) {
+                     hipEvent_t ev1 = nullptr, bool split = false) {
     const int n_inst = (int)P.desc.size();
+    if (mode == GINI_SOLVE_BATCHED && split && n_inst > 1) return run_split(c, P, iters, s, ev0, ev1);
     // one upload: descriptors, then the tile prefix
     const size_t dbytes = (P.desc.size() * sizeof(InstDesc) + 15) & ~size_t(15);
     const size_t pbytes = P.prefix.size() * sizeof(int64_t);
@@ -811,6 +915,7 @@ gini_status autotune_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst
     for (int T : {64, 128, 256}) {
         if (T > 64 && maxn <= T / 2) continue;
         cand.push_back({probe_iters, GINI_SOLVE_BATCHED, T, 0});
+        if (n_inst > 1) cand.push_back({probe_iters, GINI_SOLVE_BATCHED | GINI_SOLVE_SPLIT, T, 0});
         int64_t units = 0;
         for (int k = 0; k < n_inst; ++k) {
             const int64_t nb = (inst[k].n + T - 1) / T;
@@ -887,7 +992,8 @@ gini_status solve_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst, c
     gini_status st = make_plan(c, inst, n_inst, T, P, s);
     if (st != GINI_OK) return st;
     if (opts.iters == 0) return GINI_OK;
-    st = run_plan(c, P, opts.iters, solve_mode(opts.flags), opts.grid, s, ev0, ev1);
+    st = run_plan(c, P, opts.iters, solve_mode(opts.flags), opts.grid, s, ev0, ev1,
+                  (opts.flags & GINI_SOLVE_SPLIT) != 0);
     if (st != GINI_OK) return st;
     if (opts.flags & GINI_SOLVE_CHECK_FINITE) {
         std::vector<float> h(opts.iters);
@@ -907,8 +1013,10 @@ gini_status check_opts(gini_ctx* c, const gini_solve_opts* o) {
     const int modes = o->flags & (GINI_SOLVE_PERSISTENT | GINI_SOLVE_PLAIN | GINI_SOLVE_BATCHED);
     if (modes & (modes - 1)) return fail(c, GINI_EINVAL, "choose one of PERSISTENT, PLAIN, BATCHED");
     if (o->flags & ~(GINI_SOLVE_PERSISTENT | GINI_SOLVE_PLAIN | GINI_SOLVE_BATCHED | GINI_SOLVE_AUTOTUNE |
-                     GINI_SOLVE_CHECK_FINITE))
+                     GINI_SOLVE_CHECK_FINITE | GINI_SOLVE_SPLIT))
         return fail(c, GINI_EINVAL, "unknown solve flag");
+    if ((o->flags & GINI_SOLVE_SPLIT) && !(o->flags & GINI_SOLVE_BATCHED))
+        return fail(c, GINI_EINVAL, "SPLIT needs BATCHED");
     if (o->tile != 0 && o->tile != 64 && o->tile != 128 && o->tile != 256)
         return fail(c, GINI_EINVAL, "tile must be 0, 64, 128 or 256");
     if (o->grid < 0) return fail(c, GINI_EINVAL, "grid < 0");
@@ -1002,6 +1110,11 @@ void gini_destroy(gini_ctx* c) {
         for (hipEvent_t e : c->cm_ready)
             if (e) (void)hipEventDestroy(e);
         if (c->cm_copy) (void)hipStreamDestroy(c->cm_copy);
+        if (c->side_fork) (void)hipEventDestroy(c->side_fork);
+        for (int g = 0; g < kSplitGroups - 1; ++g) {
+            if (c->side_join[g]) (void)hipEventDestroy(c->side_join[g]);
+            if (c->side[g]) (void)hipStreamDestroy(c->side[g]);
+        }
         prof_clear(c);
         for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
         for (auto& sl : c->ring) {

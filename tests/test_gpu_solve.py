@@ -50,9 +50,10 @@ def test_modes_bitwise_identical(gm, tile):
     Zp, hp = _run(gm, probs, 7, gm.SOLVE_PLAIN, tile)
     Zb, hb = _run(gm, probs, 7, gm.SOLVE_BATCHED, tile)
     Zs, hs = _run(gm, probs, 7, gm.SOLVE_PERSISTENT, tile)
+    Zt, ht = _run(gm, probs, 7, gm.SOLVE_BATCHED | gm.SOLVE_SPLIT, tile)
     for k in range(len(SIZES)):
-        assert torch.equal(Zp[k], Zb[k]) and torch.equal(Zp[k], Zs[k]), k
-        assert torch.equal(hp[k], hb[k]) and torch.equal(hp[k], hs[k]), k
+        assert torch.equal(Zp[k], Zb[k]) and torch.equal(Zp[k], Zs[k]) and torch.equal(Zp[k], Zt[k]), k
+        assert torch.equal(hp[k], hb[k]) and torch.equal(hp[k], hs[k]) and torch.equal(hp[k], ht[k]), k
 
 
 def test_batched_equals_single_instance_runs(gm):
@@ -100,7 +101,7 @@ def test_autotune_and_solve(gm):
     probs = _instances(gm, SIZES, seed=9)
     insts = [gm.Instance(D, Z0.clone(), nu) for D, Z0, nu in probs]
     best = gm.gini_autotune(insts, 2)
-    assert best["flags"] in (gm.SOLVE_PERSISTENT, gm.SOLVE_BATCHED)
+    assert best["flags"] in (gm.SOLVE_PERSISTENT, gm.SOLVE_BATCHED, gm.SOLVE_BATCHED | gm.SOLVE_SPLIT)
     assert best["tile"] in (64, 128, 256)
     for I, (D, Z0, nu) in zip(insts, probs):
         assert torch.equal(I.Z, Z0)                 # autotune works on copies

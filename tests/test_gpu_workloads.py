@@ -195,11 +195,12 @@ def test_sweep_full(gm, orc):
     runs = {}
     for name, flags, tile in [("auto", tuned["flags"], tuned["tile"]),
                               ("batched", gm.SOLVE_BATCHED, tuned["tile"]),
+                              ("split", gm.SOLVE_BATCHED | gm.SOLVE_SPLIT, tuned["tile"]),
                               ("plain", gm.SOLVE_PLAIN, tuned["tile"])]:
         insts, hs = make()
         gm.gini_mds_solve(insts, 3, flags, tile, tuned["grid"] if name == "auto" else 0)
         runs[name] = ([I.Z.cpu() for I in insts], [h.cpu() for h in hs])
-    for name in ("batched", "plain"):
+    for name in ("batched", "split", "plain"):
         for a, b in zip(runs["auto"][0], runs[name][0]):
             assert torch.equal(a, b), name
         for a, b in zip(runs["auto"][1], runs[name][1]):
