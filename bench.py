@@ -71,25 +71,30 @@ def parse():
     return ap.parse_args()
 
 
-PROFILE = os.path.join(ROOT, "profiles", "k_stress_units_images_n10000.md")
+PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2605_25124_amd", "csrc", f)
                   for f in ("k_stress.hip", "stress_impl.hpp", "common.hpp", "kernels.hpp")]
 
 
-def measured_traffic(kernel, n, tile):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when that summary was taken on other kernel sources or
-    another launch configuration."""
+def measured_traffic(kernel, n, p, tile):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 counter
+    summary under profiles/ taken at this n, p and tile on the current kernel
+    sources, or None when there is none."""
+    digest = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()
     try:
-        text = open(PROFILE).read()
+        names = sorted(os.listdir(PROFILES))
     except OSError:
         return None
-    fields = dict(re.findall(r"^(\w+): (\S+)$", text, re.M))
-    digest = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()
-    if (fields.get("kernel") != kernel or fields.get("source_sha256") != digest
-            or fields.get("n") != str(n) or fields.get("tile") != str(tile)):
-        return None
-    return float(fields["traffic_bytes_per_launch"])
+    for name in names:
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(PROFILES, name)) as f:
+            fields = dict(re.findall(r"^(\w+): (\S+)$", f.read(), re.M))
+        if (fields.get("kernel") == kernel and fields.get("source_sha256") == digest
+                and fields.get("n") == str(n) and fields.get("p") == str(p) and fields.get("tile") == str(tile)
+                and "traffic_bytes_per_launch" in fields):
+            return float(fields["traffic_bytes_per_launch"])
+    return None
 
 
 def log(msg):
@@ -307,7 +312,7 @@ def main():
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(kname, n, best["tile"]) if mode_name == "batched" else None,
+            "traffic": measured_traffic(kname, n, p, best["tile"]) if mode_name == "batched" else None,
             "kernel": kname,
             "avg_launch_us": round(avg_ms * 1e3, 2), "alg_bytes_per_launch": alg_bytes,
             "reduce_avg_us": round(prof["reduce_ms"] * 1e3 / max(prof["reduce_launches"], 1), 2)}
