@@ -1701,10 +1701,13 @@ gini_status gini_classical_mds(gini_ctx* c, const float* Delta, int64_t n, int64
     const int Q = gmds::kMaxCmdsQ;
     constexpr int kSlots = 4;                  // Rayleigh-Ritz matrices in flight (ring)
     constexpr int kVRing = 3;                  // blocks V_t kept: the one being checked and two ahead
-    // workspace: the V ring, Y' (D^2 V), Yh (B V), then small buffers
+    // workspace: the V ring, Y = D^2 V in FP64 (two FP32 blocks Yp, Yh while
+    // the start block is formed), then small buffers
     const size_t nq = ((size_t)n * q + 63) & ~size_t(63);
     const size_t small = 2 * (size_t)Q * Q * (2 + kSlots) + 2 * (size_t)Q * Q;
-    st = ensure_select(c, ((kVRing + 2) * nq + small + gmds::gram_part_floats() + 64) * sizeof(float));
+    const size_t partf = (size_t)std::max<int64_t>(gmds::gram_part_floats(), 2 * gmds::step_part_doubles());
+    const size_t dsmall = 2 * ((size_t)Q * Q + Q);
+    st = ensure_select(c, ((kVRing + 2) * nq + small + partf + dsmall + 64) * sizeof(float));
     if (st != GINI_OK) return st;
     if (!c->cm_pin) {
         if (hipHostMalloc(reinterpret_cast<void**>(&c->cm_pin), 2 * (size_t)Q * Q * kSlots * sizeof(float),
@@ -1716,14 +1719,17 @@ gini_status gini_classical_mds(gini_ctx* c, const float* Delta, int64_t n, int64
     }
     float* Vr[kVRing];
     for (int k = 0; k < kVRing; ++k) Vr[k] = c->sel + k * nq;
-    float* Yp = c->sel + kVRing * nq;
+    double* Yd = reinterpret_cast<double*>(c->sel + kVRing * nq);
+    float* Yp = c->sel + kVRing * nq;              // start only (the memory of Yd)
     float* Yh = Yp + nq;
     float* gout = Yh + nq;                         // column sums (hi, lo)
-    float* gG = gout + 2 * (size_t)Q * Q;          // Gram matrix of B V (hi, lo)
-    float* gT = gG + 2 * (size_t)Q * Q;            // kSlots Rayleigh-Ritz matrices (hi, lo)
+    float* gG = gout + 2 * (size_t)Q * Q;          // Gram matrix (hi, lo)
+    float* gT = gG + 2 * (size_t)Q * Q;            // kSlots Rayleigh-Ritz matrices (q x q doubles each)
     float* Mdev = gT + 2 * (size_t)Q * Q * kSlots; // orthonormalising map, q x q
     float* Idev = Mdev + (size_t)Q * Q;            // identity, q x q
-    float* part = Idev + (size_t)Q * Q;            // Gram partials
+    float* part = Idev + (size_t)Q * Q;            // Gram partials (FP32 start, FP64 steps)
+    double* Md = reinterpret_cast<double*>(part + partf);   // the step's map, q x q
+    double* meand = Md + (size_t)Q * Q;                       // and its column means
     {
         std::vector<float> I((size_t)q * q, 0.f);
         for (int i = 0; i < q; ++i) I[(size_t)i * q + i] = 1.f;
@@ -1735,44 +1741,33 @@ gini_status gini_classical_mds(gini_ctx* c, const float* Delta, int64_t n, int64
         st = slot_done(c, sl, s);
         if (st != GINI_OK) return st;
     }
-    // start: a fixed pseudo-random block (xorshift64*), centred, orthonormalised
-    // (Cholesky of its Gram matrix, on the device)
+    // start: a fixed pseudo-random block, made on the device, centred and
+    // orthonormalised (Cholesky of its Gram matrix, on the device)
     {
-        std::vector<float> v0((size_t)n * q);
-        uint64_t x = 0x9E3779B97F4A7C15ull;
-        for (size_t k = 0; k < v0.size(); ++k) {
-            x ^= x >> 12;
-            x ^= x << 25;
-            x ^= x >> 27;
-            v0[k] = (float)((double)((x * 0x2545F4914F6CDD1Dull) >> 11) * (1.0 / 9007199254740992.0) - 0.5);
-        }
-        GINI_HIP(c, hipMemcpyAsync(Yp, v0.data(), v0.size() * sizeof(float), hipMemcpyHostToDevice, s));
+        GINI_HIP(c, gmds::launch_start_block(Yp, n * q, s));
         GINI_HIP(c, gmds::launch_gram(Yp, q, nullptr, 1, n, part, gout, s));
         GINI_HIP(c, gmds::launch_rowmat(Yp, q, gout, 1.f, Idev, q, n, Yh, q, s));
         GINI_HIP(c, gmds::launch_gram(Yh, q, Yh, q, n, part, gG, s));
         GINI_HIP(c, gmds::launch_chol_orth(gG, q, Mdev, s));
         GINI_HIP(c, gmds::launch_rowmat(Yh, q, nullptr, 1.f, Mdev, q, n, Vr[0], q, s));
-        GINI_HIP(c, hipStreamSynchronize(s));      // v0 is host memory
     }
-    // Step t on the device: Yh = B V_t = -1/2 H (D^2 V_t), the Rayleigh-Ritz
-    // matrix T_t = V_t^T Yh (sent to the host ring) and G = Yh^T Yh in one
-    // launch, V_{t+1} = Yh R^-1 from the Cholesky factor of G.  The host checks
-    // step t while step t+1 runs, so the GPU never waits for it; V_t stays in
-    // the ring until then.
+    // Step t on the device: Y = D^2 V_t in FP64 (one pass over Delta), then
+    // from FP64 sums over the rows of Y and V_t the Rayleigh-Ritz matrix
+    // T_t = V_t^T B V_t (sent to the host ring), the Gram matrix of
+    // B V_t = -1/2 H Y and V_{t+1} = (B V_t) R^-1 from its Cholesky factor.
+    // The host checks step t while step t+1 runs, so the GPU never waits for
+    // it; V_t stays in the ring until then.
     auto enqueue = [&](int t) -> gini_status {
         const float* V = Vr[t % kVRing];
-        float* T = gT + 2 * (size_t)Q * Q * (t % kSlots);
-        GINI_HIP(c, gmds::launch_d2v(Delta, n, ldd, V, q, Yp, s));
-        GINI_HIP(c, gmds::launch_gram(Yp, q, nullptr, 1, n, part, gout, s));
-        GINI_HIP(c, gmds::launch_rowmat(Yp, q, gout, -0.5f, Idev, q, n, Yh, q, s));
-        GINI_HIP(c, gmds::launch_gram(V, q, Yh, q, n, part, T, s, Yh, Yh, gG));
+        double* T = reinterpret_cast<double*>(gT + 2 * (size_t)Q * Q * (t % kSlots));
+        GINI_HIP(c, gmds::launch_d2v(Delta, n, ldd, V, q, Yd, s));
+        GINI_HIP(c, gmds::launch_subspace_step(Yd, V, q, n, reinterpret_cast<double*>(part), T, Md, meand,
+                                               Vr[(t + 1) % kVRing], s));
         float* land = c->cm_pin + 2 * (size_t)Q * Q * (t % kSlots);
         GINI_HIP(c, hipEventRecord(c->cm_ready[t % kSlots], s));
         GINI_HIP(c, hipStreamWaitEvent(c->cm_copy, c->cm_ready[t % kSlots], 0));
-        GINI_HIP(c, hipMemcpyAsync(land, T, 2 * (size_t)q * q * sizeof(float), hipMemcpyDeviceToHost, c->cm_copy));
+        GINI_HIP(c, hipMemcpyAsync(land, T, (size_t)q * q * sizeof(double), hipMemcpyDeviceToHost, c->cm_copy));
         GINI_HIP(c, hipEventRecord(c->cm_ev[t % kSlots], c->cm_copy));
-        GINI_HIP(c, gmds::launch_chol_orth(gG, q, Mdev, s));
-        GINI_HIP(c, gmds::launch_rowmat(Yh, q, nullptr, 1.f, Mdev, q, n, Vr[(t + 1) % kVRing], q, s));
         return GINI_OK;
     };
     std::vector<double> lam, W, prev;
@@ -1783,10 +1778,8 @@ gini_status gini_classical_mds(gini_ctx* c, const float* Delta, int64_t n, int64
             if (st != GINI_OK) return st;
         }
         GINI_HIP(c, hipEventSynchronize(c->cm_ev[chk % kSlots]));
-        const float* g = c->cm_pin + 2 * (size_t)Q * Q * (chk % kSlots);
-        std::vector<double> T((size_t)q * q);
-        for (int i = 0; i < q; ++i)
-            for (int j = 0; j < q; ++j) T[(size_t)i * q + j] = (double)g[2 * (i * q + j)] + (double)g[2 * (i * q + j) + 1];
+        const double* g = reinterpret_cast<const double*>(c->cm_pin + 2 * (size_t)Q * Q * (chk % kSlots));
+        std::vector<double> T(g, g + (size_t)q * q);
         for (int i = 0; i < q; ++i)
             for (int j = 0; j < i; ++j)
                 T[(size_t)i * q + j] = T[(size_t)j * q + i] = 0.5 * (T[(size_t)i * q + j] + T[(size_t)j * q + i]);

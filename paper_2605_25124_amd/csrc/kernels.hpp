@@ -120,8 +120,19 @@ hipError_t launch_sumsq(const float* Delta, int64_t n, int64_t ldd, int n_mat, i
                         float* out, int power, hipStream_t s);
 
 // Classical MDS (k_cmds.hip).  out = D^2 V over full rows of Delta (diagonal
-// left out), V and out n x q row-major, q <= kMaxCmdsQ.
-hipError_t launch_d2v(const float* Delta, int64_t n, int64_t ldd, const float* V, int q, float* out, hipStream_t s);
+// left out) in FP64, V (FP32) and out n x q row-major, q <= kMaxCmdsQ.
+hipError_t launch_d2v(const float* Delta, int64_t n, int64_t ldd, const float* V, int q, double* out,
+                      hipStream_t s);
+// One subspace step after launch_d2v: from Y = D^2 V and V, the Rayleigh-Ritz
+// matrix T = V^T B V (q x q doubles), the map M and mean with which
+// Vnext = (Y - 1 mean^T) M = (B V) R^-1 has orthonormal columns (B V = -1/2 H Y,
+// R the Cholesky factor of (B V)^T (B V)), and Vnext itself.  `part` holds
+// step_part_doubles() doubles; M q*q doubles; mean q doubles.
+int64_t step_part_doubles();
+// count pseudo-random values in [-1/2, 1/2), a fixed function of the index.
+hipError_t launch_start_block(float* V, int64_t count, hipStream_t s);
+hipError_t launch_subspace_step(const double* Y, const float* V, int q, int64_t n, double* part, double* T,
+                                double* M, double* mean, float* Vnext, hipStream_t s);
 // out (qa*qb (hi, lo) pairs) = A^T B over n rows (B == nullptr: column sums
 // of A, qb = 1); A2, B2, out2 (optional) a second product of the same shape
 // in the same launches.  `part` holds gram_part_floats() floats.
