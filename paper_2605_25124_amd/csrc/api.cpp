@@ -146,6 +146,17 @@ gini_status ensure_ready(gini_ctx* c) {
 
 // Copy `bytes` from host to a device staging slot on `s`; returns the device
 // pointer.  The slot is reused only after the work recorded on it has ended.
+// Uploads of at most 3 KiB travel as the argument of a one-block kernel that
+// stores them: the kernel's launch packet carries them, and no copy engine
+// is involved (its latency is most of a small copy's cost).
+constexpr int kArgBlobWords = 768;
+struct ArgBlob {
+    uint32_t w[kArgBlobWords];
+};
+__global__ void k_put_blob(ArgBlob b, uint32_t* dst, int nw) {
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) dst[i] = b.w[i];
+}
+
 gini_status upload(gini_ctx* c, const void* src, size_t bytes, hipStream_t s, void** dev, Slot** slot_out) {
     Slot& sl = c->ring[c->ring_next];
     c->ring_next = (c->ring_next + 1) % kRing;
@@ -160,8 +171,17 @@ gini_status upload(gini_ctx* c, const void* src, size_t bytes, hipStream_t s, vo
         if (hipMalloc(&sl.dev, cap) != hipSuccess) return fail(c, GINI_ENOMEM, "device staging allocation failed");
         sl.cap = cap;
     }
-    std::memcpy(sl.host, src, bytes);
-    GINI_HIP(c, hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, s));
+    if (bytes <= sizeof(ArgBlob)) {
+        ArgBlob b;
+        const int nw = (int)((bytes + 3) / 4);
+        if (nw > 0) b.w[nw - 1] = 0u;
+        std::memcpy(b.w, src, bytes);
+        hipLaunchKernelGGL(k_put_blob, dim3(1), dim3(256), 0, s, b, static_cast<uint32_t*>(sl.dev), nw);
+        GINI_HIP(c, hipGetLastError());
+    } else {
+        std::memcpy(sl.host, src, bytes);
+        GINI_HIP(c, hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, s));
+    }
     *dev = sl.dev;
     *slot_out = &sl;
     return GINI_OK;
