@@ -128,3 +128,45 @@ def test_zero_iterations_is_noop(gm):
     Z = Z0.clone()
     gm.gini_mds_solve([gm.Instance(D, Z, nu)], 0, gm.SOLVE_PERSISTENT)
     assert torch.equal(Z, Z0)
+
+
+_ABORT_CHILD = r"""
+import sys
+import numpy as np
+import torch
+sys.path.insert(0, sys.argv[1])
+from paper_2605_25124_amd import ginimds as gm, synth
+g = np.random.Generator(np.random.PCG64(11))
+insts = []
+for n in (1500, 900, 260):
+    X = synth.gaussian_mixture(g, n, 12, 3, 0.05).astype(np.float32)
+    D = gm.gini_dissim(torch.from_numpy(X).cuda(), [2.0])[0]
+    Z = torch.from_numpy((0.1 * g.standard_normal((n, 2))).astype(np.float32)).cuda()
+    insts.append(gm.Instance(D, Z, 2.0))
+try:
+    gm.gini_mds_solve(insts, 6, gm.SOLVE_PERSISTENT, 64)
+    print("persistent: completed")
+except gm.GiniError as e:
+    print("persistent: aborted:", e)
+gm.gini_mds_solve(insts, 2, gm.SOLVE_BATCHED, 64)
+torch.cuda.synchronize()
+print("batched after: ok")
+"""
+
+
+def test_persistent_wait_limit_aborts_cleanly(tmp_path):
+    # A wait limit of one clock tick, set from the host: every dependency wait
+    # of the persistent launch ends at once, the launch stops and reports the
+    # abort, and the context stays usable.
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    script = tmp_path / "abort_child.py"
+    script.write_text(_ABORT_CHILD)
+    env = dict(os.environ, GINI_SPIN_LIMIT_TICKS="1")
+    print("child: persistent solve with a one-tick wait limit", flush=True)
+    r = subprocess.run([sys.executable, str(script), root], env=env, capture_output=True, text=True, timeout=100)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "persistent: aborted" in r.stdout and "time limit" in r.stdout, r.stdout
+    assert "batched after: ok" in r.stdout, r.stdout
