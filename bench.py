@@ -115,7 +115,7 @@ def host_cpu():
     return {"nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)), "cpu_model": model}
 
 
-def cpu_leg(args, w, D, Z0, nu, p, gm, dev):
+def cpu_leg(args, w, D, Z0, nu, p, gm, dev, mixture=False):
     """The oracle timed on a bounded sample of the workload, one thread pinned
     to one core: its dissimilarity build on the first `ns` rows (the real Gini
     Delta of the sample), then descent steps on that Delta for about
@@ -153,6 +153,24 @@ def cpu_leg(args, w, D, Z0, nu, p, gm, dev):
         Dsm = O.dissim(ws.X, [2.0], O.MATCH32)[0]
         O.solve(Dsm, ws.Z0[0].astype(np.float64), 2.0, ws.iters, O.LATENT_GINI, O.MATCH32)
         t_small = time.perf_counter() - t0
+        # the Gaussian-mixture workload: its Delta (3 nu) in full, then 20
+        # descent steps at each nu (of the 500 the workload runs)
+        mix = None
+        if mixture:
+            wg = synth.workload_gmm()
+            t0 = time.perf_counter()
+            Dg = O.dissim(wg.X, wg.nus, O.MATCH32)
+            t_gd = time.perf_counter() - t0
+            ks = 20
+            t0 = time.perf_counter()
+            for q, nug in enumerate(wg.nus):
+                O.solve(Dg[q], wg.Z0[q].astype(np.float64), nug, ks, O.LATENT_GINI, O.MATCH32)
+            t_gs = time.perf_counter() - t0
+            mix = {"workload": f"Gaussian mixture n={wg.X.shape[0]} m={wg.X.shape[1]}, nu in {wg.nus}",
+                   "delta_s": round(t_gd, 2), "steps_per_nu": ks, "steps_s": round(t_gs, 2),
+                   "extrapolated_full_s": {"note": f"Delta measured; descent scaled from {ks} to {wg.iters} "
+                                                   f"steps per nu, not measured",
+                                           "value": round(t_gd + t_gs * wg.iters / ks, 1)}}
     finally:
         os.sched_setaffinity(0, old_aff)
     sp = ns * (ns - 1) // 2
@@ -165,6 +183,7 @@ def cpu_leg(args, w, D, Z0, nu, p, gm, dev):
                      f"the 200 x 10 workload and its 100 descent steps",
            "dissim_pairs_per_s": round(sp / t_delta, 1),
            "small_workload_full_s": round(t_small, 3),
+           "mixture_workload": mix,
            "extrapolated_n2": {"note": f"n^2 extrapolation from the {ns}-row sample to n={n}, not measured",
                                "dissim_build_s": round(t_delta * full / sp, 1),
                                "descent_step_s": round(full / step_rate, 3)},
@@ -365,7 +384,7 @@ def main():
     cpu = None
     errors = None
     if not args.no_cpu_baseline:
-        cpu, errors = cpu_leg(args, w, D, Z0, nu, p, gm, dev)
+        cpu, errors = cpu_leg(args, w, D, Z0, nu, p, gm, dev, mixture=not heavy)
         log(f"cpu oracle {cpu['value']:.3e} pair-evals/s; errors {json.dumps(errors)}")
 
     # ---- nu-sweep: batched persistent vs plain

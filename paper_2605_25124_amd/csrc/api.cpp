@@ -90,9 +90,8 @@ struct gini_ctx {
     // gini_classical_mds: pinned landing slots for the Rayleigh-Ritz matrices
     // of the iterations in flight, and their events
     float* cm_pin = nullptr;
+    float* cm_pin_dev = nullptr;     // the same memory as the device addresses it
     hipEvent_t cm_ev[4] = {};
-    hipEvent_t cm_ready[4] = {};
-    hipStream_t cm_copy = nullptr;   // the copies to the landing slots run beside the iteration
     // the extra streams of a split batched solve, and the fork / join events
     hipStream_t side[kSplitGroups - 1] = {};
     hipEvent_t side_fork = nullptr, side_join[kSplitGroups - 1] = {};
@@ -1127,9 +1126,6 @@ void gini_destroy(gini_ctx* c) {
         if (c->cm_pin) (void)hipHostFree(c->cm_pin);
         for (hipEvent_t e : c->cm_ev)
             if (e) (void)hipEventDestroy(e);
-        for (hipEvent_t e : c->cm_ready)
-            if (e) (void)hipEventDestroy(e);
-        if (c->cm_copy) (void)hipStreamDestroy(c->cm_copy);
         if (c->side_fork) (void)hipEventDestroy(c->side_fork);
         for (int g = 0; g < kSplitGroups - 1; ++g) {
             if (c->side_join[g]) (void)hipEventDestroy(c->side_join[g]);
@@ -1724,7 +1720,7 @@ gini_status gini_classical_mds(gini_ctx* c, const float* Delta, int64_t n, int64
     // workspace: the V ring, Y = D^2 V in FP64 (two FP32 blocks Yp, Yh while
     // the start block is formed), then small buffers
     const size_t nq = ((size_t)n * q + 63) & ~size_t(63);
-    const size_t small = 2 * (size_t)Q * Q * (2 + kSlots) + 2 * (size_t)Q * Q;
+    const size_t small = 2 * (size_t)Q * Q * 2 + 2 * (size_t)Q * Q;
     const size_t partf = (size_t)std::max<int64_t>(gmds::gram_part_floats(), 2 * gmds::step_part_doubles());
     const size_t dsmall = 2 * ((size_t)Q * Q + Q);
     st = ensure_select(c, ((kVRing + 2) * nq + small + partf + dsmall + 64) * sizeof(float));
@@ -1733,9 +1729,8 @@ gini_status gini_classical_mds(gini_ctx* c, const float* Delta, int64_t n, int64
         if (hipHostMalloc(reinterpret_cast<void**>(&c->cm_pin), 2 * (size_t)Q * Q * kSlots * sizeof(float),
                           hipHostMallocDefault) != hipSuccess)
             return fail(c, GINI_ENOMEM, "pinned landing buffer of classical MDS failed");
+        GINI_HIP(c, hipHostGetDevicePointer(reinterpret_cast<void**>(&c->cm_pin_dev), c->cm_pin, 0));
         for (auto& e : c->cm_ev) GINI_HIP(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        for (auto& e : c->cm_ready) GINI_HIP(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        GINI_HIP(c, hipStreamCreateWithFlags(&c->cm_copy, hipStreamNonBlocking));
     }
     float* Vr[kVRing];
     for (int k = 0; k < kVRing; ++k) Vr[k] = c->sel + k * nq;
@@ -1744,8 +1739,7 @@ gini_status gini_classical_mds(gini_ctx* c, const float* Delta, int64_t n, int64
     float* Yh = Yp + nq;
     float* gout = Yh + nq;                         // column sums (hi, lo)
     float* gG = gout + 2 * (size_t)Q * Q;          // Gram matrix (hi, lo)
-    float* gT = gG + 2 * (size_t)Q * Q;            // kSlots Rayleigh-Ritz matrices (q x q doubles each)
-    float* Mdev = gT + 2 * (size_t)Q * Q * kSlots; // orthonormalising map, q x q
+    float* Mdev = gG + 2 * (size_t)Q * Q;          // orthonormalising map, q x q
     float* Idev = Mdev + (size_t)Q * Q;            // identity, q x q
     float* part = Idev + (size_t)Q * Q;            // Gram partials (FP32 start, FP64 steps)
     double* Md = reinterpret_cast<double*>(part + partf);   // the step's map, q x q
@@ -1773,21 +1767,18 @@ gini_status gini_classical_mds(gini_ctx* c, const float* Delta, int64_t n, int64
     }
     // Step t on the device: Y = D^2 V_t in FP64 (one pass over Delta), then
     // from FP64 sums over the rows of Y and V_t the Rayleigh-Ritz matrix
-    // T_t = V_t^T B V_t (sent to the host ring), the Gram matrix of
+    // T_t = V_t^T B V_t (stored into the pinned host ring), the Gram matrix of
     // B V_t = -1/2 H Y and V_{t+1} = (B V_t) R^-1 from its Cholesky factor.
     // The host checks step t while step t+1 runs, so the GPU never waits for
     // it; V_t stays in the ring until then.
     auto enqueue = [&](int t) -> gini_status {
         const float* V = Vr[t % kVRing];
-        double* T = reinterpret_cast<double*>(gT + 2 * (size_t)Q * Q * (t % kSlots));
+        // T_t is stored by the step kernel straight into its pinned landing slot
+        double* T = reinterpret_cast<double*>(c->cm_pin_dev + 2 * (size_t)Q * Q * (t % kSlots));
         GINI_HIP(c, gmds::launch_d2v(Delta, n, ldd, V, q, Yd, s));
         GINI_HIP(c, gmds::launch_subspace_step(Yd, V, q, n, reinterpret_cast<double*>(part), T, Md, meand,
                                                Vr[(t + 1) % kVRing], s));
-        float* land = c->cm_pin + 2 * (size_t)Q * Q * (t % kSlots);
-        GINI_HIP(c, hipEventRecord(c->cm_ready[t % kSlots], s));
-        GINI_HIP(c, hipStreamWaitEvent(c->cm_copy, c->cm_ready[t % kSlots], 0));
-        GINI_HIP(c, hipMemcpyAsync(land, T, (size_t)q * q * sizeof(double), hipMemcpyDeviceToHost, c->cm_copy));
-        GINI_HIP(c, hipEventRecord(c->cm_ev[t % kSlots], c->cm_copy));
+        GINI_HIP(c, hipEventRecord(c->cm_ev[t % kSlots], s));
         return GINI_OK;
     };
     std::vector<double> lam, W, prev;
@@ -1840,7 +1831,6 @@ gini_status gini_classical_mds(gini_ctx* c, const float* Delta, int64_t n, int64
     st = slot_done(c, sl, s);
     if (st != GINI_OK) return st;
     GINI_HIP(c, hipStreamSynchronize(s));
-    GINI_HIP(c, hipStreamSynchronize(c->cm_copy));   // no copy outlives the call
     if (iters_done) *iters_done = chk + 1;
     for (int k = 0; k < p; ++k)
         if (eigvals && !std::isfinite(eigvals[k])) return fail(c, GINI_ENOTFINITE, "eigenvalue %d is not finite", k);
