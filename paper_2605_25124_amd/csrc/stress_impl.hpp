@@ -972,9 +972,14 @@ __global__ __launch_bounds__(kWG) void k_solve_persistent(const InstDesc* __rest
         if (tid == 0) {
             int ok = 1;
             if (__hip_atomic_load(&epoch[k], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < (uint32_t)it) {
+                // Every poll is an acquire, which invalidates this XCD's L2
+                // (the lines the running units stream from included), so the
+                // pause between polls grows, up to about 8000 cycles.
                 const uint64_t t0 = wall_clock64();
+                int naps = 1;
                 while (__hip_atomic_load(&epoch[k], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < (uint32_t)it) {
-                    __builtin_amdgcn_s_sleep(2);
+                    for (int j = 0; j < naps; ++j) __builtin_amdgcn_s_sleep(8);
+                    naps = naps < 16 ? 2 * naps : 16;
                     if (__hip_atomic_load(&ctl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != kStatusOk) {
                         ok = 0;
                         break;
@@ -997,9 +1002,12 @@ __global__ __launch_bounds__(kWG) void k_solve_persistent(const InstDesc* __rest
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const InstDesc D = dd[k];
         stress_unit<P, LAT, LOSS, T, true>(D, lu, lds);
-        __threadfence();
+        // every wave's stores have reached this XCD's L2 at the barrier; one
+        // device-scope release (an L2 writeback) by one thread then publishes
+        // them all with the count (a fence in every wave cost four)
         __syncthreads();
         if (tid == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const uint32_t old = atomicAdd(D.instcnt, 1u);
             sh_flag = (old + 1 == (uint32_t)(tri_count(D.nb) * UNITS)) ? 1 : 0;
         }
@@ -1009,9 +1017,8 @@ __global__ __launch_bounds__(kWG) void k_solve_persistent(const InstDesc* __rest
             const Comp s = instance_sigma<T, P, kWG>(D, lds);
             write_sigma(D, kModeDescent, it, s);
             for (int64_t k0 = 0; k0 < D.n; k0 += kNPT) reduce_group<P, LAT, T, kWG>(D, k0, kModeDescent, lds);
-            __threadfence();
             __syncthreads();
-            if (tid == 0) {
+            if (tid == 0) {      // the release store publishes the workgroup's updates of Z
                 __hip_atomic_store(D.instcnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(&epoch[k], (uint32_t)(it + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
