@@ -53,7 +53,7 @@ def test_select_modes_agree(gm):
     Z0 = torch.from_numpy(w.Z0[0][:900]).to(DEV)
     nus = [1.2, 1.5, 2.0, 2.5, 3.0, 4.0]
     out = [gm.gini_select_nu(X, nus, Z0, 10, folds=3, flags=f, tile=64)
-           for f in (gm.SOLVE_BATCHED, gm.SOLVE_PERSISTENT, gm.SOLVE_PLAIN)]
+           for f in (gm.SOLVE_BATCHED, gm.SOLVE_PERSISTENT, gm.SOLVE_PLAIN, gm.SOLVE_BATCHED | gm.SOLVE_SPLIT)]
     for b, mean, ks, Z in out[1:]:
         assert b == out[0][0]
         assert np.array_equal(ks, out[0][2])
