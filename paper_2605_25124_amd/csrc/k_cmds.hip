@@ -194,18 +194,15 @@ __global__ __launch_bounds__(kCW) void k_step_part(const double* __restrict__ Y,
 }
 
 // out (qa*qb (hi, lo) pairs, entry a*qb + b) = A^T B over n rows, B == nullptr
-// meaning the column sums of A (qb = 1); a launch may carry a second product
-// of the same shape (blockIdx.y = 1).  The same blocking as k_step_part, with
-// compensated FP32 sums; k_gram_final adds the kGB partials of every entry in
-// block order, so every entry has one fixed shape.
+// meaning the column sums of A (qb = 1); used for the start block.  The same
+// blocking as k_step_part, with compensated FP32 sums; k_gram_final adds the
+// kGB partials of every entry in block order, so every entry has one fixed
+// shape.
 
-__global__ __launch_bounds__(kCW) void k_gram_part(const float* __restrict__ A0, const float* __restrict__ B0,
-                                                   const float* __restrict__ A1, const float* __restrict__ B1,
-                                                   int qa, int qb, int64_t n, int64_t rows_per_block,
+__global__ __launch_bounds__(kCW) void k_gram_part(const float* __restrict__ A, const float* __restrict__ B, int qa,
+                                                   int qb, int64_t n, int64_t rows_per_block,
                                                    float* __restrict__ part) {
     __shared__ float lds[2 * kCW];
-    const float* A = blockIdx.y ? A1 : A0;
-    const float* B = blockIdx.y ? B1 : B0;
     const int ne = qa * qb;
     const int S = kCW / ne;
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
@@ -238,24 +235,21 @@ __global__ __launch_bounds__(kCW) void k_gram_part(const float* __restrict__ A0,
             x.lo = lds[2 * (k * ne + t) + 1];
             tot.add(x);
         }
-        float* pp = part + 2 * (((int64_t)blockIdx.y * kGB + blockIdx.x) * ne + t);
+        float* pp = part + 2 * ((int64_t)blockIdx.x * ne + t);
         pp[0] = tot.hi;
         pp[1] = tot.lo;
     }
 }
 
-// out_y[e] = sum over blocks of part[y][block][e] in block order, (hi, lo).
-__global__ __launch_bounds__(kCW) void k_gram_final(const float* __restrict__ part, int ne, int nprod,
-                                                    float* __restrict__ out0, float* __restrict__ out1) {
-    const int x = threadIdx.x;
-    if (x >= ne * nprod) return;
-    const int y = x / ne, e = x % ne;
-    float* out = y ? out1 : out0;
+// out[e] = sum over blocks of part[block][e] in block order, (hi, lo).
+__global__ __launch_bounds__(kCW) void k_gram_final(const float* __restrict__ part, int ne, float* __restrict__ out) {
+    const int e = threadIdx.x;
+    if (e >= ne) return;
     float h[kGB], l[kGB];
 #pragma unroll
     for (int k = 0; k < kGB; ++k) {
-        h[k] = part[2 * (((int64_t)y * kGB + k) * ne + e)];
-        l[k] = part[2 * (((int64_t)y * kGB + k) * ne + e) + 1];
+        h[k] = part[2 * ((int64_t)k * ne + e)];
+        l[k] = part[2 * ((int64_t)k * ne + e) + 1];
     }
     Comp acc;
 #pragma unroll
@@ -524,17 +518,16 @@ hipError_t launch_subspace_step(const double* Y, const float* V, int q, int64_t 
 }
 
 hipError_t launch_gram(const float* A, int qa, const float* B, int qb, int64_t n, float* part, float* out,
-                       hipStream_t s, const float* A2, const float* B2, float* out2) {
-    const int nprod = A2 ? 2 : 1;
+                       hipStream_t s) {
     const int64_t rpb = (n + kGB - 1) / kGB;
-    hipLaunchKernelGGL(k_gram_part, dim3(kGB, nprod), dim3(kCW), 0, s, A, B, A2, B2, qa, qb, n, rpb, part);
+    hipLaunchKernelGGL(k_gram_part, dim3(kGB), dim3(kCW), 0, s, A, B, qa, qb, n, rpb, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gram_final, dim3(1), dim3(kCW), 0, s, part, qa * qb, nprod, out, out2);
+    hipLaunchKernelGGL(k_gram_final, dim3(1), dim3(kCW), 0, s, part, qa * qb, out);
     return hipGetLastError();
 }
 
-int64_t gram_part_floats() { return 2 * (int64_t)kGB * 2 * kQ * kQ; }
+int64_t gram_part_floats() { return 2 * (int64_t)kGB * kQ * kQ; }
 
 hipError_t launch_chol_orth(const float* g, int q, float* M, hipStream_t s) {
     hipLaunchKernelGGL(k_chol_orth, dim3(1), dim3(64), 0, s, g, q, M);

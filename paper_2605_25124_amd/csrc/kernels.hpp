@@ -134,11 +134,10 @@ hipError_t launch_start_block(float* V, int64_t count, hipStream_t s);
 hipError_t launch_subspace_step(const double* Y, const float* V, int q, int64_t n, double* part, double* T,
                                 double* M, double* mean, float* Vnext, hipStream_t s);
 // out (qa*qb (hi, lo) pairs) = A^T B over n rows (B == nullptr: column sums
-// of A, qb = 1); A2, B2, out2 (optional) a second product of the same shape
-// in the same launches.  `part` holds gram_part_floats() floats.
+// of A, qb = 1).  `part` holds gram_part_floats() floats.
 int64_t gram_part_floats();
 hipError_t launch_gram(const float* A, int qa, const float* B, int qb, int64_t n, float* part, float* out,
-                       hipStream_t s, const float* A2 = nullptr, const float* B2 = nullptr, float* out2 = nullptr);
+                       hipStream_t s);
 // M (q x q, row-major) such that Y M has orthonormal columns, from the Gram
 // matrix g = Y^T Y (launch_gram's (hi, lo) output): Cholesky, then R^-1;
 // columns in the span of earlier ones become zero.
