@@ -19,8 +19,10 @@
  *     comment says "host".  Matrices are row-major with an explicit leading
  *     dimension (elements between the starts of consecutive rows).
  *   - Calls are asynchronous on the given stream and return once the work is
- *     enqueued, except gini_mds_solve and gini_autotune, which synchronise the
- *     stream before returning (see there).  A NULL stream is the null stream.
+ *     enqueued, except where the comment says that they synchronise it (the
+ *     calls that return host results, gini_autotune, and gini_mds_solve in
+ *     its persistent mode or with CHECK_FINITE).  A NULL stream is the null
+ *     stream.
  *   - Inputs must be finite.  Ranks compare FP32 values with IEEE < and ==, so
  *     -0 and +0 tie.
  *   - The caller owns every array it passes.  The context owns its scratch
@@ -297,13 +299,17 @@ typedef struct {
  * delta_sumsq[1])) is formed in FP64 from the compensated sigma (0 when the
  * normaliser is 0).  BATCHED | SPLIT deals the instances (largest first) into
  * two groups of about equal work and issues each group's launches on its own
- * stream (`stream`, and a stream the context owns, joined to `stream` before
- * the call returns), so that the reduction of one group runs beside the
- * stress units of the other; with one instance it is plain BATCHED.  All
- * modes give bitwise identical results for the same tile size (every
- * instance's sums have a fixed shape).  Synchronises `stream` before returning
- * (to report device-side failures); a persistent launch that stops making
- * progress aborts and returns GINI_EDEVICE.
+ * stream (`stream`, and a stream the context owns, made to wait for each
+ * other at the start and the end of the call), so that the reduction of one
+ * group runs beside the stress units of the other; with one instance it is
+ * plain BATCHED.  All modes give bitwise identical results for the same tile
+ * size (every instance's sums have a fixed shape).  PLAIN and BATCHED return
+ * once their work is enqueued on `stream` (Z and the histories are complete
+ * when `stream` reaches that point); PERSISTENT, and any call with
+ * CHECK_FINITE, synchronise `stream` before returning, to report device-side
+ * failures: a persistent launch that stops making progress aborts and returns
+ * GINI_EDEVICE.  A context's calls must be ordered: on one stream, or the
+ * caller orders the streams (they share the context's scratch).
  */
 gini_status gini_mds_solve(gini_ctx* ctx, const gini_instance* inst, int32_t n_inst,
                            const gini_solve_opts* opts, gini_stream_t stream);

@@ -791,10 +791,7 @@ gini_status run_split(gini_ctx* c, Plan& P, int iters, hipStream_t s, hipEvent_t
         GINI_HIP(c, hipStreamWaitEvent(s, c->side_join[g - 1], 0));
     }
     if (ev1) GINI_HIP(c, hipEventRecord(ev1, s));
-    st = slot_done(c, sl, s);
-    if (st != GINI_OK) return st;
-    GINI_HIP(c, hipStreamSynchronize(s));
-    return GINI_OK;
+    return slot_done(c, sl, s);
 }
 
 // ev0/ev1 (optional) are recorded right before the first and after the last
@@ -865,8 +862,10 @@ gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStr
     if (ev1) GINI_HIP(c, hipEventRecord(ev1, s));
     st = slot_done(c, sl, s);
     if (st != GINI_OK) return st;
-    GINI_HIP(c, hipStreamSynchronize(s));
+    // the other modes return once their launches are enqueued; the
+    // persistent launch is waited for, to report an abort
     if (mode == GINI_SOLVE_PERSISTENT) {
+        GINI_HIP(c, hipStreamSynchronize(s));
         gmds::SolveCtl h{};
         GINI_HIP(c, hipMemcpy(&h, c->ctl, sizeof h, hipMemcpyDeviceToHost));
         if (h.status != gmds::kStatusOk) {
@@ -1015,6 +1014,7 @@ gini_status solve_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst, c
                   (opts.flags & GINI_SOLVE_SPLIT) != 0);
     if (st != GINI_OK) return st;
     if (opts.flags & GINI_SOLVE_CHECK_FINITE) {
+        GINI_HIP(c, hipStreamSynchronize(s));
         std::vector<float> h(opts.iters);
         for (int k = 0; k < n_inst; ++k) {
             if (!inst[k].sigma_hist) continue;

@@ -464,7 +464,9 @@ def _instances(insts: Sequence[Instance]):
 
 def gini_mds_solve(insts: Sequence[Instance], iters: int, flags: int = SOLVE_PERSISTENT, tile: int = 0,
                    grid: int = 0) -> None:
-    """Fixed-step gradient descent on every instance (synchronises the stream)."""
+    """Fixed-step gradient descent on every instance, on the current stream
+    (the persistent mode and CHECK_FINITE synchronise it; the others only
+    enqueue)."""
     for I in insts:
         for h, name in ((I.sigma_hist, "sigma_hist"), (I.ks_hist, "ks_hist")):
             if h is not None and h.numel() < iters:
