@@ -283,7 +283,10 @@ typedef struct {
     int32_t flags;     /* one of PERSISTENT / PLAIN / BATCHED, or AUTOTUNE;
                           plus CHECK_FINITE; SPLIT only together with BATCHED   */
     int32_t tile;      /* 0 = library choice, else 64, 128 or 256               */
-    int32_t grid;      /* persistent workgroups; 0 = library choice             */
+    int32_t grid;      /* PERSISTENT: workgroups of the launch; PLAIN and
+                          BATCHED: threads of a reduction workgroup, 256 or
+                          1024 (results do not depend on it); 0 = library
+                          choice                                                */
 } gini_solve_opts;
 
 /*
@@ -320,7 +323,8 @@ gini_status gini_mds_solve(gini_ctx* ctx, const gini_instance* inst, int32_t n_i
  * configurations (the caller's Z and histories are not modified), and write
  * the fastest into *best (flags keep the caller's CHECK_FINITE bit).  The
  * candidates are the batched mode at every tile size (with and without
- * SPLIT when there are several instances), and the persistent mode at several
+ * SPLIT when there are several instances, with reduction workgroups of 256 and
+ * 1024 threads), and the persistent mode at several
  * grid sizes only where one iteration has no more work units than the GPU has
  * compute units (elsewhere its per-unit release costs more than two launches
  * per iteration).  The

@@ -717,7 +717,7 @@ gini_status ensure_side(gini_ctx* c) {
 // other groups' on the host, so that the GPU runs one group's reduction beside
 // the others' stress units.  An instance's partials, counters and sums are
 // those of the one-group launch, so the results are bitwise the same.
-gini_status run_split(gini_ctx* c, Plan& P, int iters, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+gini_status run_split(gini_ctx* c, Plan& P, int iters, int red_wg, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     constexpr int NG = kSplitGroups;
     const int n_inst = (int)P.desc.size();
     const int ng = std::min(NG, n_inst);
@@ -783,7 +783,7 @@ gini_status run_split(gini_ctx* c, Plan& P, int iters, hipStream_t s, hipEvent_t
             }
             ProfScope ps(c, kProfReduce, str[g], true);
             GINI_HIP(c, gmds::launch_stress_reduce(ddp, ni, G[g].rblocks, 0, P.p, P.latent, P.T, gmds::kModeDescent,
-                                                   it, G[g].maxn, str[g], ps.timer(), bmap));
+                                                   it, G[g].maxn, str[g], ps.timer(), bmap, red_wg));
         }
     }
     for (int g = 1; g < ng; ++g) {
@@ -799,7 +799,9 @@ gini_status run_split(gini_ctx* c, Plan& P, int iters, hipStream_t s, hipEvent_t
 gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStream_t s, hipEvent_t ev0 = nullptr,
                      hipEvent_t ev1 = nullptr, bool split = false) {
     const int n_inst = (int)P.desc.size();
-    if (mode == GINI_SOLVE_BATCHED && split && n_inst > 1) return run_split(c, P, iters, s, ev0, ev1);
+    // grid: the persistent launch's workgroups, else the threads of a
+    // reduction workgroup (0 = by instance size)
+    if (mode == GINI_SOLVE_BATCHED && split && n_inst > 1) return run_split(c, P, iters, grid, s, ev0, ev1);
     // one upload: descriptors, then the tile prefix
     const size_t dbytes = (P.desc.size() * sizeof(InstDesc) + 15) & ~size_t(15);
     const size_t pbytes = P.prefix.size() * sizeof(int64_t);
@@ -834,7 +836,7 @@ gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStr
                 GINI_HIP(c, gmds::launch_stress_reduce(ddp + k, 1,
                                                        gmds::reduce_block_count(P.desc[k].n, P.desc[k].nb, P.T, P.p),
                                                        P.desc[k].red_off, P.p, P.latent, P.T, gmds::kModeDescent, it,
-                                                       P.desc[k].n, s, ps.timer()));
+                                                       P.desc[k].n, s, ps.timer(), nullptr, grid));
             }
         }
     } else if (mode == GINI_SOLVE_BATCHED) {
@@ -846,7 +848,7 @@ gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStr
             }
             ProfScope ps(c, kProfReduce, s, true);
             GINI_HIP(c, gmds::launch_stress_reduce(ddp, n_inst, P.rblocks, 0, P.p, P.latent, P.T,
-                                                   gmds::kModeDescent, it, P.maxn, s, ps.timer(), dbmap));
+                                                   gmds::kModeDescent, it, P.maxn, s, ps.timer(), dbmap, grid));
         }
     } else {
         hipLaunchKernelGGL(k_reset_ctl, dim3((n_inst + 255) / 256), dim3(256), 0, s, c->ctl, c->epochs, n_inst);
@@ -926,14 +928,18 @@ gini_status autotune_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst
     std::vector<gini_solve_opts> cand;
     int64_t maxn = 0;
     for (int k = 0; k < n_inst; ++k) maxn = std::max(maxn, inst[k].n);
+    // Per tile size: the batched launches (one stream, and two streams for
+    // several instances) with reduction workgroups of 256 and 1024 threads.
     // The persistent solver pays a device-scope release (a writeback of the
     // XCD's L2) per work unit; it can only win when an iteration is one wave
     // of workgroups or less and launch latency dominates, so it is tried only
     // there.
     for (int T : {64, 128, 256}) {
         if (T > 64 && maxn <= T / 2) continue;
-        cand.push_back({probe_iters, GINI_SOLVE_BATCHED, T, 0});
-        if (n_inst > 1) cand.push_back({probe_iters, GINI_SOLVE_BATCHED | GINI_SOLVE_SPLIT, T, 0});
+        for (int rw : {256, 1024}) {
+            cand.push_back({probe_iters, GINI_SOLVE_BATCHED, T, rw});
+            if (n_inst > 1) cand.push_back({probe_iters, GINI_SOLVE_BATCHED | GINI_SOLVE_SPLIT, T, rw});
+        }
         int64_t units = 0;
         for (int k = 0; k < n_inst; ++k) {
             const int64_t nb = (inst[k].n + T - 1) / T;
@@ -1039,6 +1045,9 @@ gini_status check_opts(gini_ctx* c, const gini_solve_opts* o) {
     if (o->tile != 0 && o->tile != 64 && o->tile != 128 && o->tile != 256)
         return fail(c, GINI_EINVAL, "tile must be 0, 64, 128 or 256");
     if (o->grid < 0) return fail(c, GINI_EINVAL, "grid < 0");
+    if ((o->flags & (GINI_SOLVE_PLAIN | GINI_SOLVE_BATCHED)) && o->grid != 0 && o->grid != 256 && o->grid != 1024)
+        return fail(c, GINI_EINVAL, "grid of a plain or batched solve (threads per reduction workgroup) must be 0, "
+                                    "256 or 1024");
     return GINI_OK;
 }
 

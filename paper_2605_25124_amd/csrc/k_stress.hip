@@ -48,8 +48,8 @@ hipError_t launch_stress_units(const InstDesc* dd, int n_inst, int64_t count, in
 
 hipError_t launch_stress_reduce(const InstDesc* dd, int n_inst, int64_t blocks, int64_t q_base, int p, int latent,
                                 int T, int mode, int it, int64_t max_n, hipStream_t s, LaunchTimer tm,
-                                const int32_t* bmap) {
-    const Launch L{s, tm, max_n <= kSmallReduceN};
+                                const int32_t* bmap, int red_wg) {
+    const Launch L{s, tm, red_wg ? red_wg == kRedWGSmall : max_n <= kSmallReduceN};
     if (T == 64) return reduce_dispatch_lat<64>(dd, n_inst, bmap, blocks, q_base, p, latent, mode, it, L);
     if (T == 128) return reduce_dispatch_lat<128>(dd, n_inst, bmap, blocks, q_base, p, latent, mode, it, L);
     return reduce_dispatch_lat<256>(dd, n_inst, bmap, blocks, q_base, p, latent, mode, it, L);

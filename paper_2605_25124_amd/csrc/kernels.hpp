@@ -96,9 +96,11 @@ hipError_t launch_stress_units(const InstDesc* dd, int n_inst, int64_t count, in
 // from q_base; max_n is the largest n among them (it sizes the blocks);
 // bmap (device, optional) holds the instance of every block.
 // StressMode says what is produced; `it` indexes sigma_hist in descent mode.
+// red_wg: threads per block, 256 or 1024 (the sums have the same shape
+// either way); 0 takes 256 when max_n <= 4096, else 1024.
 hipError_t launch_stress_reduce(const InstDesc* dd, int n_inst, int64_t blocks, int64_t q_base, int p, int latent,
                                 int T, int mode, int it, int64_t max_n, hipStream_t s, LaunchTimer tm = {},
-                                const int32_t* bmap = nullptr);
+                                const int32_t* bmap = nullptr, int red_wg = 0);
 int64_t reduce_block_count(int64_t n, int64_t nb, int T, int p);
 int units_per_tile(int T, int p);
 // One launch: all instances, all iterations of the descent.

@@ -171,6 +171,7 @@ def test_solve_validation(gm):
     assert run([inst()], Opts(5, gm.SOLVE_PERSISTENT, 100, 0)) == EINVAL
     assert run([inst()], Opts(5, 1 << 10, 0, 0)) == EINVAL
     assert run([inst()], Opts(5, gm.SOLVE_SPLIT, 0, 0)) == EINVAL and "SPLIT" in _err(gm, h)
+    assert run([inst()], Opts(5, gm.SOLVE_BATCHED, 0, 512)) == EINVAL and "reduction" in _err(gm, h)
     assert run([inst()], Opts(5, gm.SOLVE_PERSISTENT | gm.SOLVE_SPLIT, 0, 0)) == EINVAL
     assert L.gini_mds_solve(h, None, 1, ctypes.byref(ok), None) == EINVAL
     L.gini_destroy(h)
