@@ -456,7 +456,8 @@ def main():
         persistent_rate = n_inst * args.persistent_iters / (time.perf_counter() - t0)
         sweep = {"workload": "16 Gaussian-mixture problems n~U{100..3000} m~U{4..64} x 8 nu in [1.1,4], p=2",
                  "instances": n_inst, "batched_mode": "persistent" if tuned["flags"] == gm.SOLVE_PERSISTENT
-                 else ("batched, two streams" if tuned["flags"] & gm.SOLVE_SPLIT else "batched"),
+                 else ("batched, two streams" if tuned["flags"] & gm.SOLVE_SPLIT else "batched")
+                 + (", caller's order" if tuned["flags"] & gm.SOLVE_CALLER_ORDER else ""),
                  "tile": tuned["tile"], "grid": tuned["grid"],
                  "batched_iters_per_s": round(batched_rate, 1), "plain_iters_per_s": round(plain_rate, 1),
                  "persistent_iters_per_s": round(persistent_rate, 1),

@@ -275,7 +275,9 @@ enum {
     GINI_SOLVE_BATCHED = 4,      /* per iteration: 2 launches for all instances */
     GINI_SOLVE_AUTOTUNE = 8,     /* choose tile, grid and mode by measurement   */
     GINI_SOLVE_CHECK_FINITE = 16, /* return GINI_ENOTFINITE if a sigma is not   */
-    GINI_SOLVE_SPLIT = 32        /* with BATCHED: two groups on two streams     */
+    GINI_SOLVE_SPLIT = 32,       /* with BATCHED: two groups on two streams     */
+    GINI_SOLVE_CALLER_ORDER = 64 /* queue the instances in the caller's order,
+                                    not largest first                          */
 };
 
 typedef struct {
@@ -305,8 +307,10 @@ typedef struct {
  * stream (`stream`, and a stream the context owns, made to wait for each
  * other at the start and the end of the call), so that the reduction of one
  * group runs beside the stress units of the other; with one instance it is
- * plain BATCHED.  All modes give bitwise identical results for the same tile
- * size (every instance's sums have a fixed shape).  PLAIN and BATCHED return
+ * plain BATCHED.  Work units and reduction blocks are queued instance by
+ * instance, largest n first (CALLER_ORDER: in the order of `inst`).  All modes
+ * and orders give bitwise identical results for the same tile size (every
+ * instance's sums have a fixed shape).  PLAIN and BATCHED return
  * once their work is enqueued on `stream` (Z and the histories are complete
  * when `stream` reaches that point); PERSISTENT, and any call with
  * CHECK_FINITE, synchronise `stream` before returning, to report device-side
@@ -322,9 +326,9 @@ gini_status gini_mds_solve(gini_ctx* ctx, const gini_instance* inst, int32_t n_i
  * instances over `probe_iters` iterations each, on copies of the
  * configurations (the caller's Z and histories are not modified), and write
  * the fastest into *best (flags keep the caller's CHECK_FINITE bit).  The
- * candidates are the batched mode at every tile size (with and without
- * SPLIT when there are several instances, with reduction workgroups of 256 and
- * 1024 threads), and the persistent mode at several
+ * candidates are the batched mode at every tile size (when there are several
+ * instances also with SPLIT and with CALLER_ORDER; each with reduction
+ * workgroups of 256 and 1024 threads), and the persistent mode at several
  * grid sizes only where one iteration has no more work units than the GPU has
  * compute units (elsewhere its per-unit release costs more than two launches
  * per iteration).  The

@@ -628,7 +628,8 @@ gini_status validate_instances(gini_ctx* c, const gini_instance* inst, int32_t n
     return GINI_OK;
 }
 
-gini_status make_plan(gini_ctx* c, const gini_instance* inst, int32_t n_inst, int T, Plan& P, hipStream_t s) {
+gini_status make_plan(gini_ctx* c, const gini_instance* inst, int32_t n_inst, int T, Plan& P, hipStream_t s,
+                      bool caller_order = false) {
     P.p = inst[0].p;
     P.latent = inst[0].latent;
     P.loss = inst[0].loss;
@@ -636,7 +637,8 @@ gini_status make_plan(gini_ctx* c, const gini_instance* inst, int32_t n_inst, in
     P.order.resize(n_inst);
     std::iota(P.order.begin(), P.order.end(), 0);
     // largest first (LPT), ties by caller order
-    std::stable_sort(P.order.begin(), P.order.end(), [&](int a, int b) { return inst[a].n > inst[b].n; });
+    if (!caller_order)
+        std::stable_sort(P.order.begin(), P.order.end(), [&](int a, int b) { return inst[a].n > inst[b].n; });
     const int pg = gmds::stored_components(P.p, P.latent);
     P.desc.resize(n_inst);
     P.prefix.assign(n_inst + 1, 0);
@@ -928,8 +930,9 @@ gini_status autotune_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst
     std::vector<gini_solve_opts> cand;
     int64_t maxn = 0;
     for (int k = 0; k < n_inst; ++k) maxn = std::max(maxn, inst[k].n);
-    // Per tile size: the batched launches (one stream, and two streams for
-    // several instances) with reduction workgroups of 256 and 1024 threads.
+    // Per tile size: the batched launches (one stream with the instances
+    // largest first or in the caller's order, and two streams, for several
+    // instances) with reduction workgroups of 256 and 1024 threads.
     // The persistent solver pays a device-scope release (a writeback of the
     // XCD's L2) per work unit; it can only win when an iteration is one wave
     // of workgroups or less and launch latency dominates, so it is tried only
@@ -938,7 +941,10 @@ gini_status autotune_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst
         if (T > 64 && maxn <= T / 2) continue;
         for (int rw : {256, 1024}) {
             cand.push_back({probe_iters, GINI_SOLVE_BATCHED, T, rw});
-            if (n_inst > 1) cand.push_back({probe_iters, GINI_SOLVE_BATCHED | GINI_SOLVE_SPLIT, T, rw});
+            if (n_inst > 1) {
+                cand.push_back({probe_iters, GINI_SOLVE_BATCHED | GINI_SOLVE_SPLIT, T, rw});
+                cand.push_back({probe_iters, GINI_SOLVE_BATCHED | GINI_SOLVE_CALLER_ORDER, T, rw});
+            }
         }
         int64_t units = 0;
         for (int k = 0; k < n_inst; ++k) {
@@ -1013,7 +1019,7 @@ gini_status solve_impl(gini_ctx* c, const gini_instance* inst, int32_t n_inst, c
     for (int k = 0; k < n_inst; ++k) maxn = std::max(maxn, inst[k].n);
     const int T = opts.tile > 0 ? opts.tile : pick_tile(maxn);
     Plan P;
-    gini_status st = make_plan(c, inst, n_inst, T, P, s);
+    gini_status st = make_plan(c, inst, n_inst, T, P, s, (opts.flags & GINI_SOLVE_CALLER_ORDER) != 0);
     if (st != GINI_OK) return st;
     if (opts.iters == 0) return GINI_OK;
     st = run_plan(c, P, opts.iters, solve_mode(opts.flags), opts.grid, s, ev0, ev1,
@@ -1038,7 +1044,7 @@ gini_status check_opts(gini_ctx* c, const gini_solve_opts* o) {
     const int modes = o->flags & (GINI_SOLVE_PERSISTENT | GINI_SOLVE_PLAIN | GINI_SOLVE_BATCHED);
     if (modes & (modes - 1)) return fail(c, GINI_EINVAL, "choose one of PERSISTENT, PLAIN, BATCHED");
     if (o->flags & ~(GINI_SOLVE_PERSISTENT | GINI_SOLVE_PLAIN | GINI_SOLVE_BATCHED | GINI_SOLVE_AUTOTUNE |
-                     GINI_SOLVE_CHECK_FINITE | GINI_SOLVE_SPLIT))
+                     GINI_SOLVE_CHECK_FINITE | GINI_SOLVE_SPLIT | GINI_SOLVE_CALLER_ORDER))
         return fail(c, GINI_EINVAL, "unknown solve flag");
     if ((o->flags & GINI_SOLVE_SPLIT) && !(o->flags & GINI_SOLVE_BATCHED))
         return fail(c, GINI_EINVAL, "SPLIT needs BATCHED");

@@ -29,6 +29,7 @@ SOLVE_BATCHED = 4
 SOLVE_AUTOTUNE = 8
 SOLVE_CHECK_FINITE = 16
 SOLVE_SPLIT = 32
+SOLVE_CALLER_ORDER = 64
 
 _STATUS = {0: "GINI_OK", 1: "GINI_EINVAL", 2: "GINI_ENOMEM", 3: "GINI_EDEVICE", 4: "GINI_ENOTFINITE",
            5: "GINI_EUNSUPPORTED"}

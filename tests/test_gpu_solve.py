@@ -53,10 +53,12 @@ def test_modes_bitwise_identical(gm, tile):
     Zt, ht = _run(gm, probs, 7, gm.SOLVE_BATCHED | gm.SOLVE_SPLIT, tile)
     others = [_run(gm, probs, 7, gm.SOLVE_BATCHED, tile, grid=rw) for rw in (256, 1024)]
     others.append(_run(gm, probs, 7, gm.SOLVE_PLAIN, tile, grid=1024))
+    others.append(_run(gm, probs, 7, gm.SOLVE_BATCHED | gm.SOLVE_CALLER_ORDER, tile))
+    others.append(_run(gm, probs, 7, gm.SOLVE_PERSISTENT | gm.SOLVE_CALLER_ORDER, tile))
     for k in range(len(SIZES)):
         assert torch.equal(Zp[k], Zb[k]) and torch.equal(Zp[k], Zs[k]) and torch.equal(Zp[k], Zt[k]), k
         assert torch.equal(hp[k], hb[k]) and torch.equal(hp[k], hs[k]) and torch.equal(hp[k], ht[k]), k
-        for Zo, ho in others:          # reduction workgroups of 256 and 1024 threads
+        for Zo, ho in others:          # reduction workgroups of 256 and 1024 threads, caller's order
             assert torch.equal(Zp[k], Zo[k]) and torch.equal(hp[k], ho[k]), k
 
 
@@ -105,7 +107,8 @@ def test_autotune_and_solve(gm):
     probs = _instances(gm, SIZES, seed=9)
     insts = [gm.Instance(D, Z0.clone(), nu) for D, Z0, nu in probs]
     best = gm.gini_autotune(insts, 2)
-    assert best["flags"] in (gm.SOLVE_PERSISTENT, gm.SOLVE_BATCHED, gm.SOLVE_BATCHED | gm.SOLVE_SPLIT)
+    assert best["flags"] in (gm.SOLVE_PERSISTENT, gm.SOLVE_BATCHED, gm.SOLVE_BATCHED | gm.SOLVE_SPLIT,
+                             gm.SOLVE_BATCHED | gm.SOLVE_CALLER_ORDER)
     if best["flags"] != gm.SOLVE_PERSISTENT:
         assert best["grid"] in (256, 1024)
     assert best["tile"] in (64, 128, 256)
