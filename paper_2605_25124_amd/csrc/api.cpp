@@ -34,12 +34,14 @@ constexpr int kMaxDissimM = 4096;
 constexpr int kErrCap = 512;        // longest error message, with its terminator
 
 struct Slot {
-    void* host = nullptr;   // pinned
-    void* dev = nullptr;
-    size_t cap = 0;
+    void* host = nullptr;   // pinned staging, made for the first upload too large for a kernel argument
+    size_t hcap = 0;
+    void* dev = nullptr;    // made for the whole ring at the first upload
+    size_t dcap = 0;
     hipEvent_t done = nullptr;
     bool used = false;
 };
+constexpr size_t kSlotBytes = 64 << 10;   // device bytes of an upload slot at first
 
 struct TableKey {
     int d;
@@ -157,18 +159,33 @@ __global__ void k_put_blob(ArgBlob b, uint32_t* dst, int nw) {
 }
 
 gini_status upload(gini_ctx* c, const void* src, size_t bytes, hipStream_t s, void** dev, Slot** slot_out) {
+    // the first upload allocates the device buffers of the whole ring, so
+    // that later calls do not pay for them one slot at a time
+    if (!c->ring[0].dev) {
+        for (int i = 0; i < kRing; ++i) {
+            if (hipMalloc(&c->ring[i].dev, kSlotBytes) != hipSuccess)
+                return fail(c, GINI_ENOMEM, "upload slot allocation failed");
+            c->ring[i].dcap = kSlotBytes;
+        }
+    }
     Slot& sl = c->ring[c->ring_next];
     c->ring_next = (c->ring_next + 1) % kRing;
     if (sl.used) GINI_HIP(c, hipEventSynchronize(sl.done));
-    if (sl.cap < bytes) {
-        if (sl.host) GINI_HIP(c, hipHostFree(sl.host));
+    if (sl.dcap < bytes) {
         if (sl.dev) GINI_HIP(c, hipFree(sl.dev));
-        sl.host = sl.dev = nullptr;
-        size_t cap = std::max<size_t>(bytes, 4096);
+        sl.dev = nullptr;
+        sl.dcap = 0;
+        if (hipMalloc(&sl.dev, bytes) != hipSuccess) return fail(c, GINI_ENOMEM, "device staging allocation failed");
+        sl.dcap = bytes;
+    }
+    if (bytes > sizeof(ArgBlob) && sl.hcap < bytes) {
+        if (sl.host) GINI_HIP(c, hipHostFree(sl.host));
+        sl.host = nullptr;
+        sl.hcap = 0;
+        const size_t cap = std::max<size_t>(bytes, 4096);
         if (hipHostMalloc(&sl.host, cap, hipHostMallocDefault) != hipSuccess)
             return fail(c, GINI_ENOMEM, "pinned staging allocation of %zu bytes failed", cap);
-        if (hipMalloc(&sl.dev, cap) != hipSuccess) return fail(c, GINI_ENOMEM, "device staging allocation failed");
-        sl.cap = cap;
+        sl.hcap = cap;
     }
     if (bytes <= sizeof(ArgBlob)) {
         ArgBlob b;
