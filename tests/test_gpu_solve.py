@@ -179,3 +179,18 @@ def test_persistent_wait_limit_aborts_cleanly(tmp_path):
     assert r.returncode == 0, r.stderr[-2000:]
     assert "persistent: aborted" in r.stdout and "time limit" in r.stdout, r.stdout
     assert "batched after: ok" in r.stdout, r.stdout
+
+
+def test_split_solve_on_a_side_stream(gm):
+    # the split launches fork from and join back to the caller's stream: run
+    # on a torch stream of its own (default priority), the results read on
+    # that stream equal those of the default stream, bitwise
+    probs = _instances(gm, SIZES, seed=21)
+    Zd, hd = _run(gm, probs, 4, gm.SOLVE_BATCHED | gm.SOLVE_SPLIT, 128)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        Zs, hs = _run(gm, probs, 4, gm.SOLVE_BATCHED | gm.SOLVE_SPLIT, 128)
+    torch.cuda.synchronize()
+    for k in range(len(SIZES)):
+        assert torch.equal(Zd[k], Zs[k]) and torch.equal(hd[k], hs[k]), k
