@@ -37,6 +37,9 @@
  *     A HIP runtime failure returns GINI_EDEVICE.
  *   - One context serves one host thread at a time.  Calls on two streams of
  *     one context share its scratch and must not overlap.
+ *   - Tracing: every compute entry point opens a ROCTx range named after
+ *     itself for the length of the call (host time), which rocprofv3
+ *     --marker-trace records beside the kernel trace.
  */
 #ifndef GINIMDS_H
 #define GINIMDS_H

@@ -4,6 +4,7 @@
 // HIP kernels; the host only prepares tables of the weight function and
 // decides what to launch.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <chrono>
@@ -1121,6 +1122,16 @@ gini_status static_scratch(gini_ctx* c, unsigned char** base) {
 }  // namespace
 
 // ======================================================================= C ABI
+// A named range around every compute entry point, which rocprofv3
+// --marker-trace shows around the entry point's launches (a call into the
+// ROCTx library that returns at once when no tool is attached).
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
+
 extern "C" {
 
 gini_status gini_create(gini_ctx** ctx, int device) {
@@ -1200,6 +1211,7 @@ gini_status gini_weight_table(int32_t d, double nu, float* W) {
 
 gini_status gini_rank(gini_ctx* c, const float* V, int64_t rows, int32_t d, int64_t ldv, int32_t* twoR, int64_t ldr,
                       gini_stream_t stream) {
+    TraceRange trace_range("gini_rank");
     if (!c) return GINI_EINVAL;
     c->err.clear();
     if (rows < 0) return fail(c, GINI_EINVAL, "rows < 0");
@@ -1224,6 +1236,7 @@ gini_status gini_rank(gini_ctx* c, const float* V, int64_t rows, int32_t d, int6
 
 gini_status gini_dissim(gini_ctx* c, const float* X, int64_t n, int32_t m, int64_t ldx, const double* nu, int32_t n_nu,
                         float* Delta, int64_t ldd, int64_t stride_nu, gini_stream_t stream) {
+    TraceRange trace_range("gini_dissim");
     if (!c) return GINI_EINVAL;
     c->err.clear();
     if (n < 1) return fail(c, GINI_EINVAL, "n = %lld < 1", (long long)n);
@@ -1287,16 +1300,19 @@ static gini_status sum_common(gini_ctx* c, const float* Delta, int64_t n, int64_
 
 gini_status gini_sumsq(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, int32_t n_mat, int64_t stride,
                        float* out, gini_stream_t stream) {
+    TraceRange trace_range("gini_sumsq");
     return sum_common(c, Delta, n, ldd, n_mat, stride, out, 2, stream);
 }
 
 gini_status gini_sum(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, int32_t n_mat, int64_t stride,
                      float* out, gini_stream_t stream) {
+    TraceRange trace_range("gini_sum");
     return sum_common(c, Delta, n, ldd, n_mat, stride, out, 1, stream);
 }
 
 gini_status gini_sammon_step(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, int32_t p, double nu,
                              gini_latent latent, double* eta, gini_stream_t stream) {
+    TraceRange trace_range("gini_sammon_step");
     if (!c) return GINI_EINVAL;
     c->err.clear();
     if (!Delta || !eta) return fail(c, GINI_EINVAL, "Delta and eta must be non-null");
@@ -1331,6 +1347,7 @@ gini_status gini_sammon_step(gini_ctx* c, const float* Delta, int64_t n, int64_t
 
 gini_status gini_stress_fwd(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, const float* Z, int32_t p,
                             int64_t ldz, double nu, gini_latent latent, float* out_sigma, gini_stream_t stream) {
+    TraceRange trace_range("gini_stress_fwd");
     return stress_common(c, Delta, n, ldd, Z, p, ldz, nu, latent, nullptr, nullptr, p, out_sigma, false,
                          GINI_LOSS_RAW, nullptr, reinterpret_cast<hipStream_t>(stream));
 }
@@ -1338,6 +1355,7 @@ gini_status gini_stress_fwd(gini_ctx* c, const float* Delta, int64_t n, int64_t 
 gini_status gini_stress_bwd(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, const float* Z, int32_t p,
                             int64_t ldz, double nu, gini_latent latent, const float* grad_out, float* gradZ,
                             int64_t ldg, float* out_sigma, gini_stream_t stream) {
+    TraceRange trace_range("gini_stress_bwd");
     return stress_common(c, Delta, n, ldd, Z, p, ldz, nu, latent, grad_out, gradZ, ldg, out_sigma, true,
                          GINI_LOSS_RAW, nullptr, reinterpret_cast<hipStream_t>(stream));
 }
@@ -1345,6 +1363,7 @@ gini_status gini_stress_bwd(gini_ctx* c, const float* Delta, int64_t n, int64_t 
 gini_status gini_stress_bwd_static(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, const float* Z,
                                    int32_t p, int64_t ldz, double nu, gini_latent latent, const float* grad_out,
                                    float* gradZ, int64_t ldg, float* out_sigma, gini_stream_t stream) {
+    TraceRange trace_range("gini_stress_bwd_static");
     if (!c) return GINI_EINVAL;
     c->err.clear();
     gini_status st = check_stress_args(c, Delta, n, ldd, Z, p, ldz, nu, latent, gradZ, ldg, out_sigma, true,
@@ -1381,6 +1400,7 @@ gini_status gini_stress_bwd_static(gini_ctx* c, const float* Delta, int64_t n, i
 gini_status gini_sammon_fwd(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, const float* delta_sum,
                             const float* Z, int32_t p, int64_t ldz, double nu, gini_latent latent, float* out_sigma,
                             gini_stream_t stream) {
+    TraceRange trace_range("gini_sammon_fwd");
     return stress_common(c, Delta, n, ldd, Z, p, ldz, nu, latent, nullptr, nullptr, p, out_sigma, false,
                          GINI_LOSS_SAMMON, delta_sum, reinterpret_cast<hipStream_t>(stream));
 }
@@ -1388,12 +1408,14 @@ gini_status gini_sammon_fwd(gini_ctx* c, const float* Delta, int64_t n, int64_t 
 gini_status gini_sammon_bwd(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, const float* delta_sum,
                             const float* Z, int32_t p, int64_t ldz, double nu, gini_latent latent,
                             const float* grad_out, float* gradZ, int64_t ldg, float* out_sigma, gini_stream_t stream) {
+    TraceRange trace_range("gini_sammon_bwd");
     return stress_common(c, Delta, n, ldd, Z, p, ldz, nu, latent, grad_out, gradZ, ldg, out_sigma, true,
                          GINI_LOSS_SAMMON, delta_sum, reinterpret_cast<hipStream_t>(stream));
 }
 
 gini_status gini_mds_solve(gini_ctx* c, const gini_instance* inst, int32_t n_inst, const gini_solve_opts* opts,
                            gini_stream_t stream) {
+    TraceRange trace_range("gini_mds_solve");
     if (!c) return GINI_EINVAL;
     c->err.clear();
     gini_status st = check_opts(c, opts);
@@ -1450,6 +1472,7 @@ gini_status gini_profile_read(gini_ctx* c, gini_profile* out) {
 
 gini_status gini_autotune(gini_ctx* c, const gini_instance* inst, int32_t n_inst, int32_t probe_iters,
                           gini_solve_opts* best, gini_stream_t stream) {
+    TraceRange trace_range("gini_autotune");
     if (!c) return GINI_EINVAL;
     c->err.clear();
     if (!best) return fail(c, GINI_EINVAL, "best must be non-null");
@@ -1496,6 +1519,7 @@ gini_status gini_select_nu(gini_ctx* c, const float* X, int64_t n, int32_t m, in
                            int32_t n_nu, const float* Z0, int64_t ldz0, const gini_select_opts* o, float* Z_out,
                            int64_t ldzo, int64_t stride_z, double* ks_mean, double* ks_fold, int32_t* best,
                            gini_stream_t stream) {
+    TraceRange trace_range("gini_select_nu");
     if (!c) return GINI_EINVAL;
     c->err.clear();
     if (!o) return fail(c, GINI_EINVAL, "opts must be non-null");
@@ -1615,6 +1639,7 @@ gini_status gini_alternate_nu(gini_ctx* c, const float* X, int64_t n, int32_t m,
                               int32_t n_nu, const float* Z0, int64_t ldz0, const gini_alternate_opts* o,
                               float* Z_out, int64_t ldzo, int32_t* nu_hist, double* ks, int32_t* best,
                               gini_stream_t stream) {
+    TraceRange trace_range("gini_alternate_nu");
     if (!c) return GINI_EINVAL;
     c->err.clear();
     if (!o) return fail(c, GINI_EINVAL, "opts must be non-null");
@@ -1729,6 +1754,7 @@ gini_status gini_alternate_nu(gini_ctx* c, const float* X, int64_t n, int32_t m,
 gini_status gini_classical_mds(gini_ctx* c, const float* Delta, int64_t n, int64_t ldd, int32_t p, int32_t max_iters,
                                double tol, float* Z, int64_t ldz, double* eigvals, int32_t* iters_done,
                                gini_stream_t stream) {
+    TraceRange trace_range("gini_classical_mds");
     if (!c) return GINI_EINVAL;
     c->err.clear();
     if (!Delta || !Z) return fail(c, GINI_EINVAL, "Delta and Z must be non-null");
@@ -1871,6 +1897,7 @@ gini_status gini_classical_mds(gini_ctx* c, const float* Delta, int64_t n, int64
 
 gini_status gini_standardize(gini_ctx* c, const float* X, int64_t n, int32_t m, int64_t ldx, float* Y, int64_t ldy,
                              float* stats, gini_stream_t stream) {
+    TraceRange trace_range("gini_standardize");
     if (!c) return GINI_EINVAL;
     c->err.clear();
     if (!X || !Y) return fail(c, GINI_EINVAL, "X and Y must be non-null");
