@@ -194,3 +194,21 @@ def test_split_solve_on_a_side_stream(gm):
     torch.cuda.synchronize()
     for k in range(len(SIZES)):
         assert torch.equal(Zd[k], Zs[k]) and torch.equal(hd[k], hs[k]), k
+
+
+@pytest.mark.parametrize("flags", ["BATCHED", "PERSISTENT"])
+def test_checkpoint_resume_bitwise(gm, flags):
+    """The descent's whole state is the configuration Z (the step size is a
+    fixed function of n, p and nu), so a run stopped after 3 steps, saved to
+    host memory and resumed from that copy for 4 more steps ends bitwise where
+    a 7-step run ends, with the same stress history."""
+    fl = getattr(gm, "SOLVE_" + flags)
+    probs = _instances(gm, [(300, 8), (1100, 20)], seed=11)
+    Zfull, hfull = _run(gm, probs, 7, fl, 128)
+    Za, ha = _run(gm, probs, 3, fl, 128)
+    saved = [z.numpy().copy() for z in Za]                  # the checkpoint
+    resumed = [(D, torch.from_numpy(s).to(DEV), nu) for (D, _, nu), s in zip(probs, saved)]
+    Zb, hb = _run(gm, resumed, 4, fl, 128)
+    for k in range(len(probs)):
+        assert torch.equal(Zb[k], Zfull[k]), k
+        assert torch.equal(torch.cat([ha[k], hb[k]]), hfull[k]), k
