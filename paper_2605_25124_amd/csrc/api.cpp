@@ -799,7 +799,7 @@ gini_status run_split(gini_ctx* c, Plan& P, int iters, int red_wg, hipStream_t s
             {
                 ProfScope ps(c, kProfTile, str[g], true);
                 GINI_HIP(c, gmds::launch_stress_units(ddp, ni, G[g].tiles, 0, P.p, P.latent, P.T, true, P.loss,
-                                                      str[g], ps.timer()));
+                                                      str[g], ps.timer(), (it & 1) != 0));
             }
             ProfScope ps(c, kProfReduce, str[g], true);
             GINI_HIP(c, gmds::launch_stress_reduce(ddp, ni, G[g].rblocks, 0, P.p, P.latent, P.T, gmds::kModeDescent,
@@ -850,7 +850,7 @@ gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStr
                 {
                     ProfScope ps(c, kProfTile, s, true);
                     GINI_HIP(c, gmds::launch_stress_units(ddp + k, 1, nu, P.desc[k].tile_off, P.p, P.latent, P.T,
-                                                          true, P.loss, s, ps.timer()));
+                                                          true, P.loss, s, ps.timer(), (it & 1) != 0));
                 }
                 ProfScope ps(c, kProfReduce, s, true);
                 GINI_HIP(c, gmds::launch_stress_reduce(ddp + k, 1,
@@ -864,7 +864,7 @@ gini_status run_plan(gini_ctx* c, Plan& P, int iters, int mode, int grid, hipStr
             {
                 ProfScope ps(c, kProfTile, s, true);
                 GINI_HIP(c, gmds::launch_stress_units(ddp, n_inst, P.tiles, 0, P.p, P.latent, P.T, true, P.loss, s,
-                                                      ps.timer()));
+                                                      ps.timer(), (it & 1) != 0));
             }
             ProfScope ps(c, kProfReduce, s, true);
             GINI_HIP(c, gmds::launch_stress_reduce(ddp, n_inst, P.rblocks, 0, P.p, P.latent, P.T,

@@ -41,9 +41,10 @@ static hipError_t reduce_dispatch_lat(const InstDesc* dd, int n_inst, const int3
 }
 
 hipError_t launch_stress_units(const InstDesc* dd, int n_inst, int64_t count, int64_t q_base, int p, int latent, int T,
-                               bool grad, int loss, hipStream_t s, LaunchTimer tm) {
-    if (loss == kLossSammon) return launch_units_sammon(dd, n_inst, count, q_base, p, latent, T, grad, s, tm);
-    return units_dispatch<kLossRaw>(dd, n_inst, count, q_base, p, latent, T, grad, Launch{s, tm});
+                               bool grad, int loss, hipStream_t s, LaunchTimer tm, bool reverse) {
+    if (loss == kLossSammon)
+        return launch_units_sammon(dd, n_inst, count, q_base, p, latent, T, grad, s, tm, reverse);
+    return units_dispatch<kLossRaw>(dd, n_inst, count, q_base, p, latent, T, grad, Launch{s, tm, false, reverse});
 }
 
 hipError_t launch_stress_reduce(const InstDesc* dd, int n_inst, int64_t blocks, int64_t q_base, int p, int latent,

@@ -89,8 +89,10 @@ hipError_t launch_dissim(const DissimArgs& a, hipStream_t s);
 
 // Stream global work units q_base .. q_base+count-1 of the n_inst instances
 // described by `dd` (device; sorted by tile_off): tile partials only.
+// reverse: workgroups take the units last to first (the partials and sums do
+// not depend on the order).
 hipError_t launch_stress_units(const InstDesc* dd, int n_inst, int64_t count, int64_t q_base, int p, int latent, int T,
-                               bool grad, int loss, hipStream_t s, LaunchTimer tm = {});
+                               bool grad, int loss, hipStream_t s, LaunchTimer tm = {}, bool reverse = false);
 // Reduce the partials of every instance; `blocks` is the sum over instances
 // of reduce_block_count (instances sorted by red_off); blocks are numbered
 // from q_base; max_n is the largest n among them (it sizes the blocks);

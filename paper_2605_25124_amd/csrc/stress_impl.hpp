@@ -850,9 +850,11 @@ constexpr int units_waves() {
 
 template <int P, int LAT, int LOSS, int T, bool GRAD>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(units_waves<P, LAT, LOSS, T>())))
-void k_stress_units(const InstDesc* __restrict__ dd, int n_inst, int64_t q_base) {
+void k_stress_units(const InstDesc* __restrict__ dd, int n_inst, int64_t q_base, int rev) {
     __shared__ float lds[unit_lds_floats<P, T>()];
-    const int64_t q = (int64_t)blockIdx.x + q_base;
+    // rev: the launch takes its units last to first, so that it starts on the
+    // tiles the previous launch read last (still in the memory-side cache)
+    const int64_t q = (int64_t)(rev ? gridDim.x - 1 - blockIdx.x : blockIdx.x) + q_base;
     const int k = find_instance(dd, n_inst, q);
     const InstDesc D = dd[k];
     stress_unit<P, LAT, LOSS, T, GRAD>(D, q - D.tile_off, lds);
@@ -1037,6 +1039,7 @@ struct Launch {
     hipStream_t s;
     LaunchTimer tm;
     bool small = false;     // reduction launch: every instance has at most kSmallReduceN points
+    bool rev = false;       // stress-units launch: units in reverse order
 };
 
 // Up to this many points per instance the reduction runs in blocks of
@@ -1057,8 +1060,10 @@ template <int P, int LAT, int LOSS, int T>
 static hipError_t units_impl(const InstDesc* dd, int n_inst, int64_t count, int64_t qb, bool grad, const Launch& L) {
     if (count <= 0) return hipSuccess;
     if (grad)
-        return launch_k(k_stress_units<P, LAT, LOSS, T, true>, dim3((unsigned)count), dim3(kWG), L, dd, n_inst, qb);
-    return launch_k(k_stress_units<P, LAT, LOSS, T, false>, dim3((unsigned)count), dim3(kWG), L, dd, n_inst, qb);
+        return launch_k(k_stress_units<P, LAT, LOSS, T, true>, dim3((unsigned)count), dim3(kWG), L, dd, n_inst, qb,
+                        (int)L.rev);
+    return launch_k(k_stress_units<P, LAT, LOSS, T, false>, dim3((unsigned)count), dim3(kWG), L, dd, n_inst, qb,
+                    (int)L.rev);
 }
 
 template <int LOSS, int LAT, int T>
@@ -1118,7 +1123,7 @@ static const void* persistent_table(int p, int latent, int T) {
 
 // Defined in k_stress_sammon.hip (the Sammon-stress instantiations).
 hipError_t launch_units_sammon(const InstDesc* dd, int n_inst, int64_t count, int64_t q_base, int p, int latent,
-                               int T, bool grad, hipStream_t s, LaunchTimer tm);
+                               int T, bool grad, hipStream_t s, LaunchTimer tm, bool reverse);
 const void* persistent_ptr_sammon(int p, int latent, int T);
 
 }  // namespace gmds
