@@ -1833,7 +1833,7 @@ gini_status gini_classical_mds(gini_ctx* c, const float* Delta, int64_t n, int64
         const float* V = Vr[t % kVRing];
         // T_t is stored by the step kernel straight into its pinned landing slot
         double* T = reinterpret_cast<double*>(c->cm_pin_dev + 2 * (size_t)Q * Q * (t % kSlots));
-        GINI_HIP(c, gmds::launch_d2v(Delta, n, ldd, V, q, Yd, s));
+        GINI_HIP(c, gmds::launch_d2v(Delta, n, ldd, V, q, Yd, s, (t & 1) != 0));
         GINI_HIP(c, gmds::launch_subspace_step(Yd, V, q, n, reinterpret_cast<double*>(part), T, Md, meand,
                                                Vr[(t + 1) % kVRing], s));
         GINI_HIP(c, hipEventRecord(c->cm_ev[t % kSlots], s));

@@ -31,12 +31,14 @@ __host__ __device__ constexpr int d2v_rows(int q) { return q <= 6 ? 8 : 4; }
 
 template <bool VEC, int Q>
 __global__ __launch_bounds__(kCW) __attribute__((amdgpu_waves_per_eu(2))) void k_d2v(const float* __restrict__ Delta, int64_t n, int64_t ldd,
-                                             const float* __restrict__ V, double* __restrict__ out) {
+                                             const float* __restrict__ V, double* __restrict__ out, int rev) {
     constexpr int q = Q;
     constexpr int kRows = d2v_rows(Q);
     constexpr int kW = kCW / 64;
     __shared__ double lds[kW][kRows * Q];
-    const int64_t i0 = (int64_t)blockIdx.x * kRows;
+    // rev: the row blocks are taken last to first, so that a pass starts on
+    // the rows the previous pass read last (still in the memory-side cache)
+    const int64_t i0 = (int64_t)(rev ? gridDim.x - 1 - blockIdx.x : blockIdx.x) * kRows;
     const int nr = (int)min<int64_t>(kRows, n - i0);
     double acc[kRows][Q];
 #pragma unroll
@@ -480,24 +482,25 @@ hipError_t launch_start_block(float* V, int64_t count, hipStream_t s) {
 
 template <int Q>
 static void d2v_q(bool vec, hipStream_t s, const float* Delta, int64_t n, int64_t ldd, const float* V,
-                  double* out) {
+                  double* out, int rev) {
     const dim3 grid((unsigned)((n + d2v_rows(Q) - 1) / d2v_rows(Q)));
-    if (vec) hipLaunchKernelGGL((k_d2v<true, Q>), grid, dim3(kCW), 0, s, Delta, n, ldd, V, out);
-    else hipLaunchKernelGGL((k_d2v<false, Q>), grid, dim3(kCW), 0, s, Delta, n, ldd, V, out);
+    if (vec) hipLaunchKernelGGL((k_d2v<true, Q>), grid, dim3(kCW), 0, s, Delta, n, ldd, V, out, rev);
+    else hipLaunchKernelGGL((k_d2v<false, Q>), grid, dim3(kCW), 0, s, Delta, n, ldd, V, out, rev);
 }
 
 hipError_t launch_d2v(const float* Delta, int64_t n, int64_t ldd, const float* V, int q, double* out,
-                      hipStream_t s) {
+                      hipStream_t s, bool reverse) {
     const bool vec = (reinterpret_cast<uintptr_t>(Delta) & 15u) == 0 && (ldd % 4) == 0;
+    const int rev = reverse ? 1 : 0;
     switch (q) {
-        case 1: d2v_q<1>(vec, s, Delta, n, ldd, V, out); break;
-        case 2: d2v_q<2>(vec, s, Delta, n, ldd, V, out); break;
-        case 3: d2v_q<3>(vec, s, Delta, n, ldd, V, out); break;
-        case 4: d2v_q<4>(vec, s, Delta, n, ldd, V, out); break;
-        case 5: d2v_q<5>(vec, s, Delta, n, ldd, V, out); break;
-        case 6: d2v_q<6>(vec, s, Delta, n, ldd, V, out); break;
-        case 7: d2v_q<7>(vec, s, Delta, n, ldd, V, out); break;
-        default: d2v_q<8>(vec, s, Delta, n, ldd, V, out); break;
+        case 1: d2v_q<1>(vec, s, Delta, n, ldd, V, out, rev); break;
+        case 2: d2v_q<2>(vec, s, Delta, n, ldd, V, out, rev); break;
+        case 3: d2v_q<3>(vec, s, Delta, n, ldd, V, out, rev); break;
+        case 4: d2v_q<4>(vec, s, Delta, n, ldd, V, out, rev); break;
+        case 5: d2v_q<5>(vec, s, Delta, n, ldd, V, out, rev); break;
+        case 6: d2v_q<6>(vec, s, Delta, n, ldd, V, out, rev); break;
+        case 7: d2v_q<7>(vec, s, Delta, n, ldd, V, out, rev); break;
+        default: d2v_q<8>(vec, s, Delta, n, ldd, V, out, rev); break;
     }
     return hipGetLastError();
 }

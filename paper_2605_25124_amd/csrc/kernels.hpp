@@ -125,8 +125,9 @@ hipError_t launch_sumsq(const float* Delta, int64_t n, int64_t ldd, int n_mat, i
 
 // Classical MDS (k_cmds.hip).  out = D^2 V over full rows of Delta (diagonal
 // left out) in FP64, V (FP32) and out n x q row-major, q <= kMaxCmdsQ.
+// reverse: workgroups take the row blocks last to first (same results).
 hipError_t launch_d2v(const float* Delta, int64_t n, int64_t ldd, const float* V, int q, double* out,
-                      hipStream_t s);
+                      hipStream_t s, bool reverse = false);
 // One subspace step after launch_d2v: from Y = D^2 V and V, the Rayleigh-Ritz
 // matrix T = V^T B V (q x q doubles), the map M and mean with which
 // Vnext = (Y - 1 mean^T) M = (B V) R^-1 has orthonormal columns (B V = -1/2 H Y,
